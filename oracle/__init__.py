@@ -1,0 +1,222 @@
+"""ctypes front end of the CPU oracle (TEST INFRASTRUCTURE ONLY).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg import this
+package; the HIP product path never does.  All arrays are host numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from .build import LIB, build
+
+ABSENT = -(1 << 31)
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = C.CDLL(LIB)
+        vp, i64, i32p, u8p, f32p, f64p = C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p
+        sig = {
+            "orc_map_new": ([], vp), "orc_map_free": ([vp], None),
+            "orc_map_insert": ([vp, i32p, i32p, i64, i32p], C.c_int),
+            "orc_map_find": ([vp, i32p, i64, i32p], C.c_int),
+            "orc_map_erase": ([vp, i32p, i64, i32p], C.c_int),
+            "orc_map_apply": ([vp, u8p, i32p, i32p, i64, i32p], C.c_int),
+            "orc_map_size": ([vp], i64),
+            "orc_map_export": ([vp, i32p, i32p, i64], i64),
+            "orc_scene_new": ([vp], vp), "orc_scene_free": ([vp], None),
+            "orc_integrate_frame": ([vp, f32p, u8p, f32p, C.c_uint32], C.c_int),
+            "orc_last_touched": ([vp, i32p, i64], i64),
+            "orc_last_new": ([vp, i32p, i64], i64),
+            "orc_last_mc_updated": ([vp, i32p, i64], i64),
+            "orc_n_blocks": ([vp], i64),
+            "orc_export_blocks": ([vp, i32p, i64], i64),
+            "orc_read_blocks": ([vp, i32p, i64, f64p, u8p, u8p, i32p], C.c_int),
+            "orc_write_blocks": ([vp, i32p, i64, f32p, u8p, u8p, C.c_uint32], C.c_int),
+            "orc_extract_mc": ([vp, i32p, i64, u8p, u8p], C.c_int),
+            "orc_stored_mc": ([vp, i32p, i64, u8p, u8p], C.c_int),
+            "orc_updated_since": ([vp, C.c_uint64, i64, i32p, C.c_void_p], i64),
+            "orc_log_length": ([vp], C.c_uint64),
+            "orc_scene_error": ([vp], C.c_int),
+        }
+        optional = {
+            "orc_diff_new": ([vp], vp), "orc_diff_free": ([vp], None),
+            "orc_diff_loss": ([vp, f64p, C.c_double, f64p], C.c_double),
+            "orc_diff_grad": ([vp, f64p, f64p], C.c_int),
+            "orc_diff_info": ([vp, C.c_void_p, C.c_void_p, f64p], i64),
+        }
+        for name, (args, res) in list(sig.items()) + list(optional.items()):
+            if not hasattr(L, name):
+                if name in optional:
+                    continue
+                raise RuntimeError(f"oracle library lacks {name}")
+            fn = getattr(L, name)
+            fn.argtypes, fn.restype = args, res
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data
+
+
+def _keys(keys):
+    k = np.ascontiguousarray(keys, dtype=np.int32).reshape(-1, 3)
+    return k, k.shape[0]
+
+
+class Map:
+    """std::unordered_map semantics; batches run serially in index order."""
+
+    def __init__(self):
+        self.h = lib().orc_map_new()
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().orc_map_free(self.h)
+            self.h = None
+
+    def insert(self, keys, vals):
+        k, n = _keys(keys)
+        v = np.ascontiguousarray(vals, np.int32)
+        out = np.empty(n, np.int32)
+        rc = lib().orc_map_insert(self.h, _p(k), _p(v), n, _p(out))
+        return out, rc
+
+    def find(self, keys):
+        k, n = _keys(keys)
+        out = np.empty(n, np.int32)
+        lib().orc_map_find(self.h, _p(k), n, _p(out))
+        return out
+
+    def erase(self, keys):
+        k, n = _keys(keys)
+        out = np.empty(n, np.int32)
+        rc = lib().orc_map_erase(self.h, _p(k), n, _p(out))
+        return out, rc
+
+    def apply(self, ops, keys, vals):
+        k, n = _keys(keys)
+        o = np.ascontiguousarray(ops, np.uint8)
+        v = np.ascontiguousarray(vals, np.int32)
+        out = np.empty(n, np.int32)
+        rc = lib().orc_map_apply(self.h, _p(o), _p(k), _p(v), n, _p(out))
+        return out, rc
+
+    def size(self):
+        return int(lib().orc_map_size(self.h))
+
+    def export(self):
+        n = self.size()
+        k = np.empty((n, 3), np.int32)
+        v = np.empty(n, np.int32)
+        lib().orc_map_export(self.h, _p(k), _p(v), n)
+        return k, v
+
+
+class OrcParams(C.Structure):
+    _fields_ = [("pool_blocks", C.c_int64), ("log_capacity", C.c_int64),
+                ("voxel_size", C.c_float), ("trunc", C.c_float),
+                ("width", C.c_int32), ("height", C.c_int32),
+                ("fx", C.c_float), ("fy", C.c_float), ("cx", C.c_float), ("cy", C.c_float),
+                ("depth_min", C.c_float), ("depth_max", C.c_float)]
+
+
+def make_params(vol, cam) -> OrcParams:
+    return OrcParams(vol.pool_blocks, vol.log_capacity, vol.voxel_size, vol.trunc, cam.width,
+                     cam.height, cam.fx, cam.fy, cam.cx, cam.cy, vol.depth_min, vol.depth_max)
+
+
+def pose32(pose) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(pose, np.float64).reshape(3, 4), np.float32)
+
+
+class Scene:
+    """Block-hashed TSDF volume: allocation, integration, MC voxels, update log."""
+
+    def __init__(self, vol, cam):
+        self.params = make_params(vol, cam)
+        self.h = lib().orc_scene_new(C.byref(self.params))
+        if not self.h:
+            raise ValueError("invalid oracle scene parameters")
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().orc_scene_free(self.h)
+            self.h = None
+
+    def integrate(self, depth, rgb, pose, frame_id: int) -> int:
+        d = np.ascontiguousarray(depth, np.float32)
+        c = None if rgb is None else np.ascontiguousarray(rgb, np.uint8)
+        P = pose32(pose)
+        return lib().orc_integrate_frame(self.h, _p(d), _p(c), _p(P), frame_id)
+
+    def _keylist(self, fn):
+        n = fn(self.h, None, 0)
+        k = np.empty((n, 3), np.int32)
+        fn(self.h, _p(k), n)
+        return k
+
+    def last_touched(self):
+        return self._keylist(lib().orc_last_touched)
+
+    def last_new(self):
+        return self._keylist(lib().orc_last_new)
+
+    def last_mc_updated(self):
+        return self._keylist(lib().orc_last_mc_updated)
+
+    def blocks(self):
+        return self._keylist(lib().orc_export_blocks)
+
+    def n_blocks(self):
+        return int(lib().orc_n_blocks(self.h))
+
+    def read(self, keys):
+        k, n = _keys(keys)
+        F = np.empty((n, 512), np.float64)
+        W = np.empty((n, 512), np.uint8)
+        rgb = np.empty((n, 512, 3), np.uint8)
+        found = np.empty(n, np.int32)
+        lib().orc_read_blocks(self.h, _p(k), n, _p(F), _p(W), _p(rgb), _p(found))
+        return F, W, rgb, found
+
+    def write(self, keys, F, W, rgb, frame_id: int) -> int:
+        k, n = _keys(keys)
+        F = np.ascontiguousarray(F, np.float32)
+        W = np.ascontiguousarray(W, np.uint8)
+        c = None if rgb is None else np.ascontiguousarray(rgb, np.uint8)
+        return lib().orc_write_blocks(self.h, _p(k), n, _p(F), _p(W), _p(c), frame_id)
+
+    def extract_mc(self, keys):
+        k, n = _keys(keys)
+        mc = np.empty((n, 512), np.uint8)
+        rgb = np.empty((n, 512, 3), np.uint8)
+        lib().orc_extract_mc(self.h, _p(k), n, _p(mc), _p(rgb))
+        return mc, rgb
+
+    def stored_mc(self, keys):
+        k, n = _keys(keys)
+        mc = np.empty((n, 512), np.uint8)
+        rgb = np.empty((n, 512, 3), np.uint8)
+        lib().orc_stored_mc(self.h, _p(k), n, _p(mc), _p(rgb))
+        return mc, rgb
+
+    def updated_since(self, cursor: int, cap: int):
+        k = np.empty((max(cap, 0), 3), np.int32)
+        nxt = np.zeros(1, np.uint64)
+        n = lib().orc_updated_since(self.h, cursor, cap, _p(k), nxt.ctypes.data)
+        return k[:n], int(nxt[0])
+
+    def log_length(self):
+        return int(lib().orc_log_length(self.h))
+
+    def error(self):
+        return int(lib().orc_scene_error(self.h))
