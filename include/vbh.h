@@ -1,0 +1,212 @@
+/* vbh.h - C ABI of the MI355X voxel-block-hashing hot path.
+ *
+ * Implements the data-parallel server path of SLAMCast (Stotko, Krumpen, Hullin,
+ * Weinmann, Klein; IEEE TVCG 2019, arXiv 1805.03709):
+ *   - a thread-safe GPU hash map/set from int3 block coordinates to int32 values with
+ *     concurrent retrieval, insertion and removal that always succeed below capacity
+ *     and keep keys unique (Sec. 5, "Hash Map and Set Data Structures");
+ *   - voxel block hashing reconstruction (Sec. 4.1): block allocation along the
+ *     truncation band of every depth ray and TSDF / weight / colour fusion;
+ *   - the server's MC voxel block representation (Sec. 4.2): per voxel a Marching
+ *     Cubes case index (1 byte) plus colour (3 bytes), cut to zero for indices 0 and
+ *     255, recomputed for every updated block and its seven negative neighbours;
+ *   - per-client streaming state (Sec. 4.2): blocks updated since a client cursor,
+ *     with reconnection from cursor 0 returning every block.
+ *
+ * Conventions shared by every entry point
+ *   Keys: int32 [n][3] (x,y,z) block coordinates, each in [-2^20, 2^20).
+ *   Voxel g (int3) sits at world point g * voxel_size; block B = floor(g / 8); local id
+ *   l = (g.x-8B.x) + 8 (g.y-8B.y) + 64 (g.z-8B.z) (x fastest); a block has 512 voxels.
+ *   Camera: OpenCV (x right, y down, z forward); pose_c2w is the row-major 3x4 [R|t]
+ *   mapping camera to world; depth is camera z in metres, 0 (or NaN) = invalid.
+ *   Pointers prefixed d_ are device pointers, h_ host pointers.  `stream` is a
+ *   hipStream_t (NULL = the null stream).  Every call only enqueues work on `stream`
+ *   unless documented as synchronising; the caller keeps all buffers alive until that
+ *   work completes.  No pointer is retained after a call returns.
+ *   One host thread may use a handle at a time, and all work on one handle must be
+ *   ordered on a single stream (the library's own concurrency is on the device).
+ *
+ * Errors
+ *   Calls return VBH_OK (0) or a negative code.  Argument errors are detected on the
+ *   host.  Errors found by kernels (a key out of range, a full table, pool or log, an
+ *   expired bounded wait) are recorded in a sticky device word; vbh_map_status /
+ *   vbh_scene_status synchronise, return the first recorded code and clear it.  No
+ *   key is ever dropped silently: an operation that could not be performed reports an
+ *   error status.
+ */
+#ifndef VBH_H
+#define VBH_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VBH_OK 0
+#define VBH_EINVAL (-1)      /* bad argument, key out of range, frame id not increasing */
+#define VBH_ENOMEM (-2)      /* device allocation failed */
+#define VBH_EHIP (-3)        /* a HIP runtime call failed */
+#define VBH_EFULL_TABLE (-4) /* no EMPTY slot left on a probe sequence */
+#define VBH_EFULL_POOL (-5)  /* voxel block pool exhausted */
+#define VBH_EFULL_LOG (-6)   /* update log full */
+#define VBH_ESPIN (-7)       /* a bounded wait for a concurrent insert expired */
+
+#define VBH_ABSENT INT32_MIN /* find() result for a missing key; reserved as a value */
+
+/* Operation codes of mixed batches. */
+#define VBH_OP_INSERT 0
+#define VBH_OP_FIND 1
+#define VBH_OP_ERASE 2
+
+/* Home-slot hash: 0 = the spatial hash (x p1 xor y p2 xor z p3) mod n with the primes
+ * of Sec. 5 (Retrieval), 1 = 64-bit finalizer mix of the packed key. */
+#define VBH_HASH_SPATIAL 0
+#define VBH_HASH_MIX64 1
+
+const char *vbh_strerror(int code);
+int vbh_version(void);
+
+/* ======================================================================= hash map
+ * Concurrent map from int3 keys to int32 values (Sec. 5).  Open addressing in a
+ * power-of-two table; a batch of n operations runs as n concurrent device threads.  The
+ * outcome of a batch equals that of some serial order of its operations (for batches
+ * whose insert, find and erase keys are pairwise disjoint the outcome is unique). */
+typedef struct vbh_map vbh_map;
+
+/* slots: power of two in [64, 2^31].  Allocates 16 B per slot on the current device. */
+int vbh_map_create(uint64_t slots, int32_t hash_kind, vbh_map **out);
+void vbh_map_destroy(vbh_map *m);
+
+/* Insert-if-absent (Sec. 5, Insertion).  d_status[i] = 1 inserted, 0 already present
+ * (the stored value is kept), VBH_EINVAL for a key out of range, VBH_EFULL_TABLE when
+ * no slot was free.  d_vals must not contain VBH_ABSENT. */
+int vbh_insert(vbh_map *m, const int32_t *d_keys, const int32_t *d_vals, int64_t n, int32_t *d_status,
+               void *stream);
+/* Retrieval (Sec. 5): d_vals_out[i] = stored value or VBH_ABSENT. */
+int vbh_find(vbh_map *m, const int32_t *d_keys, int64_t n, int32_t *d_vals_out, void *stream);
+/* Removal (Sec. 5): d_status[i] = 1 erased, 0 absent. */
+int vbh_erase(vbh_map *m, const int32_t *d_keys, int64_t n, int32_t *d_status, void *stream);
+/* Mixed batch: d_ops[i] in {VBH_OP_INSERT, VBH_OP_FIND, VBH_OP_ERASE}; d_out[i] as for
+ * the single-kind calls.  d_vals is read for inserts only (may be NULL if none). */
+int vbh_apply(vbh_map *m, const uint8_t *d_ops, const int32_t *d_keys, const int32_t *d_vals, int64_t n,
+              int32_t *d_out, void *stream);
+/* Synchronising: live keys and tombstones (erased slots awaiting vbh_map_rebuild). */
+int vbh_map_size(vbh_map *m, int64_t *h_live, int64_t *h_tombstones, void *stream);
+/* Synchronising: writes up to cap live (key, value) pairs in slot order; *h_count = number
+ * of live keys (may exceed cap). */
+int vbh_map_export(vbh_map *m, int32_t *d_keys, int32_t *d_vals, int64_t cap, int64_t *h_count, void *stream);
+/* Re-inserts the live entries into a fresh table of the same size, dropping tombstones.
+ * Must not overlap other work on the map (it is stream-ordered). */
+int vbh_map_rebuild(vbh_map *m, void *stream);
+/* Removes every key. */
+int vbh_map_clear(vbh_map *m, void *stream);
+/* Synchronising: first error recorded by kernels since the last call (then cleared). */
+int vbh_map_status(vbh_map *m, void *stream);
+
+/* ========================================================================= scene
+ * A voxel block hashing volume (Sec. 4.1) plus the server's MC voxel block
+ * representation and update log (Sec. 4.2), resident in device memory:
+ *   hash table   16 B x slots            key -> block pool index
+ *   TSDF pool    8 B x 512 x pool_blocks  float F (metres, clamped to [-trunc, trunc])
+ *                                         + uint32 (W | R<<8 | G<<16 | B<<24)
+ *   MC pool      4 B x 512 x pool_blocks  uint32 (index | R<<8 | G<<16 | B<<24)
+ *   update log   8 B x log_capacity       (frame, block) in append order
+ */
+typedef struct vbh_scene vbh_scene;
+
+typedef struct vbh_params {
+    uint64_t slots;        /* hash slots, power of two in [64, 2^31] */
+    int64_t pool_blocks;   /* voxel block capacity, in [1, 2^30] */
+    int64_t log_capacity;  /* update-log entries, >= 1 */
+    float voxel_size;      /* metres, > 0 */
+    float trunc;           /* truncation band half-width mu, metres, >= voxel_size */
+    int32_t width, height; /* depth image size, > 0 */
+    float fx, fy, cx, cy;  /* pinhole intrinsics in pixels */
+    float depth_min;       /* valid depth range [depth_min, depth_max] */
+    float depth_max;
+    int32_t hash_kind;     /* VBH_HASH_* */
+} vbh_params;
+
+typedef struct vbh_stats {
+    int64_t n_touched;       /* last frame: blocks allocated or touched by the band */
+    int64_t n_new;           /* last frame: newly inserted blocks */
+    int64_t n_mc;            /* last frame: blocks whose MC voxels were recomputed */
+    int64_t n_voxel_updates; /* last frame: voxels whose TSDF was updated */
+    int64_t n_blocks;        /* allocated blocks */
+    uint64_t log_length;     /* update-log entries so far */
+    uint32_t last_frame;     /* frame id of the last update */
+    int32_t error;           /* first sticky error (not cleared) */
+    int64_t total_touched;   /* sums over every update since creation */
+    int64_t total_mc;
+    int64_t total_voxel_updates;
+} vbh_stats;
+
+int vbh_scene_create(const vbh_params *p, vbh_scene **out);
+void vbh_scene_destroy(vbh_scene *s);
+
+/* Fuse one depth frame (Sec. 4.1 voxel block hashing; Sec. 4.2 MC update):
+ *   1. allocation: every valid pixel puts 2m+1 samples (m = round(trunc/voxel_size)) at
+ *      camera depths (d - trunc) + s voxel_size on its ray; each sample's block is
+ *      inserted (a new block takes a zeroed pool block) and marked touched;
+ *   2. integration: every voxel of a touched block is projected to its nearest pixel;
+ *      unless the pixel is invalid or sdf = d - z < -trunc, F <- (W F + min(sdf,trunc))
+ *      / (W+1), W <- min(W+1, 255), colour <- rounded running mean;
+ *   3. MC update: the touched blocks and their existing seven negative neighbours get
+ *      their 512 MC voxels recomputed, their MC stamp set to frame_id and one log entry
+ *      each.
+ * d_depth float32 [H*W]; d_rgb uint8 [H*W*3] or NULL (colour left unchanged); pose_c2w
+ * is a HOST pointer to 12 floats, copied by value; frame_id > 0 and greater than every
+ * previous frame id of this scene (else VBH_EINVAL). */
+int vbh_integrate_frame(vbh_scene *s, const float *d_depth, const uint8_t *d_rgb, const float *pose_c2w,
+                        uint32_t frame_id, void *stream);
+
+/* MC voxels (Sec. 4.2) recomputed from the current TSDF for n blocks: d_mc uint8
+ * [n*512] case indices (bit k set iff corner k, Lorensen-Cline order (0,0,0) (1,0,0)
+ * (1,1,0) (0,1,0) (0,0,1) (1,0,1) (1,1,1) (0,1,1), has F < 0; 0 if any corner lies in a
+ * missing block or has W = 0; indices 0 and 255 cut to 0), d_rgb uint8 [n*512*3] or
+ * NULL (colour of the voxel, 0 where cut).  Missing blocks yield zeros. */
+int vbh_extract_mc_indices(vbh_scene *s, const int32_t *d_keys, int64_t n, uint8_t *d_mc, uint8_t *d_rgb,
+                           void *stream);
+/* MC voxels as kept in the MC pool by the last update of each block (same layout). */
+int vbh_stored_mc(vbh_scene *s, const int32_t *d_keys, int64_t n, uint8_t *d_mc, uint8_t *d_rgb, void *stream);
+
+/* Streaming state (Sec. 4.2): walks the update log from position `cursor` and returns,
+ * in log order, up to cap blocks whose entry is live (the block's latest MC update);
+ * cursor 0 therefore yields every block once (reconnection).  Writes d_keys_out [cap][3],
+ * *d_count (int64) and *d_next_cursor (uint64: position after the last returned entry if
+ * cap entries were returned, else the log end).  Device-side outputs; does not sync. */
+int vbh_updated_blocks_since(vbh_scene *s, uint64_t cursor, int64_t cap, int32_t *d_keys_out, int64_t *d_count,
+                             uint64_t *d_next_cursor, void *stream);
+
+/* Synchronising: first error recorded by kernels since the last call (then cleared). */
+int vbh_scene_status(vbh_scene *s, void *stream);
+/* Synchronising: counters of the last frame and of the scene. */
+int vbh_scene_stats(vbh_scene *s, vbh_stats *h_out, void *stream);
+/* Synchronising: up to cap allocated block keys in pool order; *h_count = total. */
+int vbh_scene_export_blocks(vbh_scene *s, int32_t *d_keys, int64_t cap, int64_t *h_count, void *stream);
+/* Synchronising: keys of the last frame's touched blocks / MC-updated blocks. */
+int vbh_scene_last_touched(vbh_scene *s, int32_t *d_keys, int64_t cap, int64_t *h_count, void *stream);
+int vbh_scene_last_mc(vbh_scene *s, int32_t *d_keys, int64_t cap, int64_t *h_count, void *stream);
+/* Voxel state of n blocks: d_F float32 [n*512], d_W uint8 [n*512], d_rgb uint8
+ * [n*512*3] (each may be NULL), d_found int32 [n] (may be NULL).  Missing: zeros. */
+int vbh_scene_read_blocks(vbh_scene *s, const int32_t *d_keys, int64_t n, float *d_F, uint8_t *d_W,
+                          uint8_t *d_rgb, int32_t *d_found, void *stream);
+/* Load voxel state for n distinct keys (allocating absent blocks), then refresh the MC
+ * voxels of those blocks and their seven negative neighbours as update frame_id (same
+ * rules as vbh_integrate_frame).  d_rgb may be NULL (colour 0). */
+int vbh_scene_write_blocks(vbh_scene *s, const int32_t *d_keys, int64_t n, const float *d_F, const uint8_t *d_W,
+                           const uint8_t *d_rgb, uint32_t frame_id, void *stream);
+
+/* Stage timing.  When enabled, vbh_integrate_frame records a HIP event pair around each
+ * of its kernels on the caller's stream (band allocation, integration, MC update-set
+ * marking, MC extraction).  vbh_scene_timing synchronises the stream and returns, per
+ * stage, the summed kernel milliseconds and the number of frames measured since the
+ * last call (then resets).  ms_out must hold VBH_N_STAGES doubles. */
+#define VBH_N_STAGES 4
+int vbh_scene_enable_timing(vbh_scene *s, int32_t enable);
+int vbh_scene_timing(vbh_scene *s, double *ms_out, int64_t *h_frames, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VBH_H */

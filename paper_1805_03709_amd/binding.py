@@ -1,0 +1,305 @@
+"""ctypes binding of libvbh.so (include/vbh.h).
+
+Argument marshalling only: every step of the hot path runs in the library's HIP kernels.
+Device buffers are torch tensors on a HIP device (PyTorch supplies memory and streams);
+work is enqueued on torch's current stream.  torch is imported before the library is
+loaded so both share one HIP runtime.  If the library is not built this module raises -
+there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+from .build import LIB
+
+VBH_OK, VBH_EINVAL, VBH_ENOMEM, VBH_EHIP = 0, -1, -2, -3
+VBH_EFULL_TABLE, VBH_EFULL_POOL, VBH_EFULL_LOG, VBH_ESPIN = -4, -5, -6, -7
+VBH_ABSENT = -(1 << 31)
+VBH_OP_INSERT, VBH_OP_FIND, VBH_OP_ERASE = 0, 1, 2
+VBH_HASH_SPATIAL, VBH_HASH_MIX64 = 0, 1
+
+_lib = None
+
+
+class VbhError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        msg = _load().vbh_strerror(code).decode() if _lib is not None else str(code)
+        super().__init__(f"{what}: {msg} ({code})" if what else f"{msg} ({code})")
+
+
+class vbh_params(C.Structure):
+    _fields_ = [("slots", C.c_uint64), ("pool_blocks", C.c_int64), ("log_capacity", C.c_int64),
+                ("voxel_size", C.c_float), ("trunc", C.c_float),
+                ("width", C.c_int32), ("height", C.c_int32),
+                ("fx", C.c_float), ("fy", C.c_float), ("cx", C.c_float), ("cy", C.c_float),
+                ("depth_min", C.c_float), ("depth_max", C.c_float), ("hash_kind", C.c_int32)]
+
+
+class vbh_stats(C.Structure):
+    _fields_ = [("n_touched", C.c_int64), ("n_new", C.c_int64), ("n_mc", C.c_int64),
+                ("n_voxel_updates", C.c_int64), ("n_blocks", C.c_int64), ("log_length", C.c_uint64),
+                ("last_frame", C.c_uint32), ("error", C.c_int32), ("total_touched", C.c_int64),
+                ("total_mc", C.c_int64), ("total_voxel_updates", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_V, _I64, _U64, _I32, _P = C.c_void_p, C.c_int64, C.c_uint64, C.c_int32, C.c_void_p
+SIGNATURES = {
+    "vbh_strerror": ([C.c_int], C.c_char_p),
+    "vbh_version": ([], C.c_int),
+    "vbh_map_create": ([_U64, _I32, C.POINTER(_V)], C.c_int),
+    "vbh_map_destroy": ([_V], None),
+    "vbh_insert": ([_V, _P, _P, _I64, _P, _V], C.c_int),
+    "vbh_find": ([_V, _P, _I64, _P, _V], C.c_int),
+    "vbh_erase": ([_V, _P, _I64, _P, _V], C.c_int),
+    "vbh_apply": ([_V, _P, _P, _P, _I64, _P, _V], C.c_int),
+    "vbh_map_size": ([_V, C.POINTER(_I64), C.POINTER(_I64), _V], C.c_int),
+    "vbh_map_export": ([_V, _P, _P, _I64, C.POINTER(_I64), _V], C.c_int),
+    "vbh_map_rebuild": ([_V, _V], C.c_int),
+    "vbh_map_clear": ([_V, _V], C.c_int),
+    "vbh_map_status": ([_V, _V], C.c_int),
+    "vbh_scene_create": ([C.POINTER(vbh_params), C.POINTER(_V)], C.c_int),
+    "vbh_scene_destroy": ([_V], None),
+    "vbh_integrate_frame": ([_V, _P, _P, C.POINTER(C.c_float), C.c_uint32, _V], C.c_int),
+    "vbh_extract_mc_indices": ([_V, _P, _I64, _P, _P, _V], C.c_int),
+    "vbh_stored_mc": ([_V, _P, _I64, _P, _P, _V], C.c_int),
+    "vbh_updated_blocks_since": ([_V, _U64, _I64, _P, _P, _P, _V], C.c_int),
+    "vbh_scene_status": ([_V, _V], C.c_int),
+    "vbh_scene_stats": ([_V, C.POINTER(vbh_stats), _V], C.c_int),
+    "vbh_scene_export_blocks": ([_V, _P, _I64, C.POINTER(_I64), _V], C.c_int),
+    "vbh_scene_last_touched": ([_V, _P, _I64, C.POINTER(_I64), _V], C.c_int),
+    "vbh_scene_last_mc": ([_V, _P, _I64, C.POINTER(_I64), _V], C.c_int),
+    "vbh_scene_read_blocks": ([_V, _P, _I64, _P, _P, _P, _P, _V], C.c_int),
+    "vbh_scene_write_blocks": ([_V, _P, _I64, _P, _P, _P, C.c_uint32, _V], C.c_int),
+    "vbh_scene_enable_timing": ([_V, _I32], C.c_int),
+    "vbh_scene_timing": ([_V, C.POINTER(C.c_double), C.POINTER(_I64), _V], C.c_int),
+}
+STAGES = ("alloc", "integrate", "mc_mark", "mc_extract")
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            raise ImportError(f"{LIB} is not built; run paper_1805_03709_amd/build.py "
+                              "(or __graft_entry__.build()) first")
+        L = C.CDLL(LIB)
+        for name, (args, res) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.argtypes, fn.restype = args, res
+        _lib = L
+    return _lib
+
+
+def lib():
+    """The loaded C library with typed entry points (same names as include/vbh.h)."""
+    return _load()
+
+
+def exported_names():
+    return list(SIGNATURES)
+
+
+def _check(rc: int, what: str):
+    if rc != VBH_OK:
+        raise VbhError(rc, what)
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t, dtype=None, n=None, name="tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a torch tensor on a HIP device")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if n is not None and t.numel() < n:
+        raise ValueError(f"{name} has {t.numel()} elements, needs {n}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _keys(keys):
+    if keys.dim() != 2 or keys.shape[1] != 3:
+        raise ValueError("keys must be int32 [n, 3]")
+    return _ptr(keys, torch.int32, name="keys"), keys.shape[0]
+
+
+class Map:
+    """Concurrent int3 -> int32 hash map on the device (vbh_map_*)."""
+
+    def __init__(self, slots: int, hash_kind: int = VBH_HASH_SPATIAL):
+        h = C.c_void_p()
+        _check(lib().vbh_map_create(slots, hash_kind, C.byref(h)), "vbh_map_create")
+        self.h, self.slots = h, slots
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().vbh_map_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def vbh_insert(self, keys, vals, status=None):
+        kp, n = _keys(keys)
+        status = torch.empty(n, dtype=torch.int32, device=keys.device) if status is None else status
+        _check(lib().vbh_insert(self.h, kp, _ptr(vals, torch.int32, n, "vals"), n,
+                                _ptr(status, torch.int32, n, "status"), _stream()), "vbh_insert")
+        return status
+
+    def vbh_find(self, keys, out=None):
+        kp, n = _keys(keys)
+        out = torch.empty(n, dtype=torch.int32, device=keys.device) if out is None else out
+        _check(lib().vbh_find(self.h, kp, n, _ptr(out, torch.int32, n, "out"), _stream()), "vbh_find")
+        return out
+
+    def vbh_erase(self, keys, status=None):
+        kp, n = _keys(keys)
+        status = torch.empty(n, dtype=torch.int32, device=keys.device) if status is None else status
+        _check(lib().vbh_erase(self.h, kp, n, _ptr(status, torch.int32, n, "status"), _stream()), "vbh_erase")
+        return status
+
+    def vbh_apply(self, ops, keys, vals, out=None):
+        kp, n = _keys(keys)
+        out = torch.empty(n, dtype=torch.int32, device=keys.device) if out is None else out
+        _check(lib().vbh_apply(self.h, _ptr(ops, torch.uint8, n, "ops"), kp, _ptr(vals, torch.int32, n, "vals"),
+                               n, _ptr(out, torch.int32, n, "out"), _stream()), "vbh_apply")
+        return out
+
+    def vbh_map_size(self):
+        live, tomb = C.c_int64(), C.c_int64()
+        _check(lib().vbh_map_size(self.h, C.byref(live), C.byref(tomb), _stream()), "vbh_map_size")
+        return live.value, tomb.value
+
+    def vbh_map_export(self, device="cuda"):
+        live, _ = self.vbh_map_size()
+        keys = torch.empty((max(live, 1), 3), dtype=torch.int32, device=device)
+        vals = torch.empty(max(live, 1), dtype=torch.int32, device=device)
+        cnt = C.c_int64()
+        _check(lib().vbh_map_export(self.h, _ptr(keys), _ptr(vals), live, C.byref(cnt), _stream()),
+               "vbh_map_export")
+        return keys[:cnt.value], vals[:cnt.value]
+
+    def vbh_map_rebuild(self):
+        _check(lib().vbh_map_rebuild(self.h, _stream()), "vbh_map_rebuild")
+
+    def vbh_map_clear(self):
+        _check(lib().vbh_map_clear(self.h, _stream()), "vbh_map_clear")
+
+    def vbh_map_status(self) -> int:
+        return int(lib().vbh_map_status(self.h, _stream()))
+
+
+def make_params(vol, cam, hash_kind: int = VBH_HASH_SPATIAL) -> vbh_params:
+    return vbh_params(vol.slots, vol.pool_blocks, vol.log_capacity, vol.voxel_size, vol.trunc,
+                      cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy, vol.depth_min,
+                      vol.depth_max, hash_kind)
+
+
+class Scene:
+    """Block-hashed TSDF volume with MC voxel pool and update log (vbh_scene_*)."""
+
+    def __init__(self, params: vbh_params):
+        self.params = params
+        h = C.c_void_p()
+        _check(lib().vbh_scene_create(C.byref(params), C.byref(h)), "vbh_scene_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().vbh_scene_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def vbh_integrate_frame(self, depth, rgb, pose_c2w, frame_id: int):
+        p = self.params
+        n = p.width * p.height
+        pose = (C.c_float * 12)(*[float(x) for x in torch.as_tensor(pose_c2w, dtype=torch.float64).reshape(-1)[:12]])
+        _check(lib().vbh_integrate_frame(self.h, _ptr(depth, torch.float32, n, "depth"),
+                                         _ptr(rgb, torch.uint8, 3 * n, "rgb"), pose, frame_id, _stream()),
+               "vbh_integrate_frame")
+
+    def vbh_extract_mc_indices(self, keys, with_rgb=True):
+        kp, n = _keys(keys)
+        mc = torch.empty((n, 512), dtype=torch.uint8, device=keys.device)
+        rgb = torch.empty((n, 512, 3), dtype=torch.uint8, device=keys.device) if with_rgb else None
+        _check(lib().vbh_extract_mc_indices(self.h, kp, n, _ptr(mc), _ptr(rgb), _stream()),
+               "vbh_extract_mc_indices")
+        return mc, rgb
+
+    def vbh_stored_mc(self, keys, with_rgb=True):
+        kp, n = _keys(keys)
+        mc = torch.empty((n, 512), dtype=torch.uint8, device=keys.device)
+        rgb = torch.empty((n, 512, 3), dtype=torch.uint8, device=keys.device) if with_rgb else None
+        _check(lib().vbh_stored_mc(self.h, kp, n, _ptr(mc), _ptr(rgb), _stream()), "vbh_stored_mc")
+        return mc, rgb
+
+    def vbh_updated_blocks_since(self, cursor: int, cap: int, device="cuda"):
+        keys = torch.empty((max(cap, 1), 3), dtype=torch.int32, device=device)
+        meta = torch.zeros(2, dtype=torch.int64, device=device)  # [count, next cursor]
+        _check(lib().vbh_updated_blocks_since(self.h, cursor, cap, _ptr(keys), C.c_void_p(meta.data_ptr()),
+                                              C.c_void_p(meta.data_ptr() + 8), _stream()),
+               "vbh_updated_blocks_since")
+        return keys, meta
+
+    def vbh_scene_status(self) -> int:
+        return int(lib().vbh_scene_status(self.h, _stream()))
+
+    def vbh_scene_stats(self) -> dict:
+        st = vbh_stats()
+        _check(lib().vbh_scene_stats(self.h, C.byref(st), _stream()), "vbh_scene_stats")
+        return st.as_dict()
+
+    def _keylist(self, fn, name, device):
+        cnt = C.c_int64()
+        _check(fn(self.h, None, 0, C.byref(cnt), _stream()), name)
+        keys = torch.empty((max(cnt.value, 1), 3), dtype=torch.int32, device=device)
+        _check(fn(self.h, _ptr(keys), cnt.value, C.byref(cnt), _stream()), name)
+        return keys[:cnt.value]
+
+    def vbh_scene_export_blocks(self, device="cuda"):
+        return self._keylist(lib().vbh_scene_export_blocks, "vbh_scene_export_blocks", device)
+
+    def vbh_scene_last_touched(self, device="cuda"):
+        return self._keylist(lib().vbh_scene_last_touched, "vbh_scene_last_touched", device)
+
+    def vbh_scene_last_mc(self, device="cuda"):
+        return self._keylist(lib().vbh_scene_last_mc, "vbh_scene_last_mc", device)
+
+    def vbh_scene_read_blocks(self, keys):
+        kp, n = _keys(keys)
+        F = torch.empty((n, 512), dtype=torch.float32, device=keys.device)
+        W = torch.empty((n, 512), dtype=torch.uint8, device=keys.device)
+        rgb = torch.empty((n, 512, 3), dtype=torch.uint8, device=keys.device)
+        found = torch.empty(n, dtype=torch.int32, device=keys.device)
+        _check(lib().vbh_scene_read_blocks(self.h, kp, n, _ptr(F), _ptr(W), _ptr(rgb), _ptr(found), _stream()),
+               "vbh_scene_read_blocks")
+        return F, W, rgb, found
+
+    def vbh_scene_enable_timing(self, enable: bool = True):
+        _check(lib().vbh_scene_enable_timing(self.h, 1 if enable else 0), "vbh_scene_enable_timing")
+
+    def vbh_scene_timing(self):
+        """{stage: summed kernel ms}, frames measured (synchronising; resets)."""
+        ms = (C.c_double * len(STAGES))()
+        frames = C.c_int64()
+        _check(lib().vbh_scene_timing(self.h, ms, C.byref(frames), _stream()), "vbh_scene_timing")
+        return dict(zip(STAGES, list(ms))), frames.value
+
+    def vbh_scene_write_blocks(self, keys, F, W, rgb, frame_id: int):
+        kp, n = _keys(keys)
+        _check(lib().vbh_scene_write_blocks(self.h, kp, n, _ptr(F, torch.float32, 512 * n, "F"),
+                                            _ptr(W, torch.uint8, 512 * n, "W"),
+                                            _ptr(rgb, torch.uint8, 1536 * n, "rgb"), frame_id, _stream()),
+               "vbh_scene_write_blocks")

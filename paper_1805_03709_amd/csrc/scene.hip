@@ -1,0 +1,975 @@
+// Voxel block hashing volume with the server's MC voxel representation (Sec. 4.1-4.2):
+// band allocation, TSDF fusion, MC voxel extraction, update log - kernels and C ABI.
+//
+// Every discrete decision (band-sample block keys, voxel->pixel index, depth validity,
+// the -trunc skip) is computed in IEEE float32 in the operation order written in the
+// comments, with contraction off and correctly rounded division, so its outcome is fully
+// determined by the float32 inputs.
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "device.hpp"
+#include "host.hpp"
+#include "vbh.h"
+
+using namespace vbh;
+
+namespace vbh {
+int table_init(Slot *T, uint64_t n, hipStream_t st);
+}
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / 64;
+constexpr int kChunk = 2048;  // log entries per workgroup chunk in the paged walk
+constexpr int kRing = 8;      // per-frame counter ring
+
+struct FrameCounters {
+    unsigned int n_touched;
+    unsigned int n_new;
+    unsigned int n_mc;
+    unsigned int pad0;
+    unsigned long long voxel_updates;
+    unsigned long long pad1;
+};
+
+struct Counters {
+    FrameCounters fc[kRing];
+    unsigned long long pool_next;  // pool blocks handed out (may exceed capacity)
+    unsigned long long log_len;    // log entries written or attempted
+    unsigned long long tot_touched;  // sums over all updates so far
+    unsigned long long tot_mc;
+    unsigned long long tot_voxel_updates;
+    uint32_t err;
+    uint32_t pad[7];
+};
+
+// Device view of a scene, passed by value to kernels.
+struct Dev {
+    Slot *T;
+    uint64_t mask;
+    int kind;
+    float *F;            // [P][512]
+    uint32_t *WRGB;      // [P][512] W | R<<8 | G<<16 | B<<24
+    uint32_t *MCV;       // [P][512] index | R<<8 | G<<16 | B<<24
+    uint64_t *pool_key;  // [P]
+    uint32_t *mc_stamp;  // [P]
+    int32_t *touched;    // [slots] slot indices
+    int32_t *mclist;     // [P] pool indices
+    uint64_t *log;       // [L] (frame << 32) | pool
+    int64_t *prefix;     // [max_chunks + 1] scratch of the paged walk
+    int64_t pool_cap;
+    uint64_t log_cap;
+    Counters *C;
+};
+
+// Camera, pose and volume constants of one frame.
+struct Frame {
+    float P[12];  // camera-to-world, row-major [R|t]
+    float fx, fy, cx, cy;
+    int W, H;
+    float dmin, dmax;
+    float vs, mu;
+    int m_band;
+};
+
+__device__ __forceinline__ bool depth_valid(float d, const Frame &f) {
+    return d > 0.0f && d >= f.dmin && d <= f.dmax;
+}
+
+// ------------------------------------------------------------------ allocation
+// One wave per 8x8 pixel tile; lane = lx + 8 ly.  Each valid pixel takes 2m+1 band
+// samples at camera depth lam = (d - mu) + s*vs:
+//   xn = ((float)u - cx) / fx, yn = ((float)v - cy) / fy, pc = (lam*xn, lam*yn, lam),
+//   pw_i = ((R_i0 pc_x + R_i1 pc_y) + R_i2 pc_z) + t_i,  B_i = floor(pw_i / (8 vs)).
+// A sample whose key equals the lane's previous sample or the same sample of the left
+// or upper lane is skipped (that lane handles the key), which removes most duplicate
+// probes before they reach the table.  The first thread to raise a block's frame stamp
+// appends the slot to the touched list (wave-aggregated).
+__global__ void __launch_bounds__(kBlock) k_alloc(Dev S, Frame fr, const float *__restrict__ depth, uint32_t frame,
+                                                  int seq) {
+    FrameCounters *fc = &S.C->fc[seq & (kRing - 1)];
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+        FrameCounters z = {};
+        S.C->fc[(seq + 2) & (kRing - 1)] = z;
+    }
+    const int lane = lane_id();
+    const int wave = threadIdx.x >> 6;
+    const int lx = lane & 7, ly = lane >> 3;
+    const int u = (blockIdx.x * 2 + (wave & 1)) * 8 + lx;
+    const int v = (blockIdx.y * 2 + (wave >> 1)) * 8 + ly;
+    const bool inb = u < fr.W && v < fr.H;
+    const float d = inb ? depth[int64_t(v) * fr.W + u] : 0.0f;
+    const bool valid = inb && depth_valid(d, fr);
+    const float xn = (float(u) - fr.cx) / fr.fx;
+    const float yn = (float(v) - fr.cy) / fr.fy;
+    const float bs = 8.0f * fr.vs;
+    uint64_t prev = kEmpty;
+    for (int s = 0; s <= 2 * fr.m_band; ++s) {
+        const float lam = (d - fr.mu) + float(s) * fr.vs;
+        bool ok = valid && lam > 0.0f;
+        uint64_t key = kEmpty;
+        int32_t B[3] = {0, 0, 0};
+        if (ok) {
+            const float pc[3] = {lam * xn, lam * yn, lam};
+            for (int i = 0; i < 3; ++i) {
+                const float pw = ((fr.P[i * 4 + 0] * pc[0] + fr.P[i * 4 + 1] * pc[1]) + fr.P[i * 4 + 2] * pc[2]) +
+                                 fr.P[i * 4 + 3];
+                const float q = floorf(pw / bs);
+                if (!(q >= -1048576.0f && q < 1048576.0f)) ok = false;
+                B[i] = ok ? int32_t(q) : 0;
+            }
+            if (ok)
+                key = pack_key(B[0], B[1], B[2]);
+            else
+                raise_err(&S.C->err, kErrKeyRange);
+        }
+        const uint64_t left = __shfl(key, (lane + 63) & 63);
+        const uint64_t up = __shfl(key, (lane + 56) & 63);
+        const bool dup = key == prev || (lx > 0 && key == left) || (ly > 0 && key == up);
+        const bool work = ok && !dup;
+        bool append = false, fresh = false;
+        int64_t slot = -1;
+        if (work) {
+            bool claimed;
+            slot = probe_claim(S.T, S.mask, key, home_slot(B[0], B[1], B[2], key, S.kind, S.mask), claimed);
+            if (slot < 0) {
+                raise_err(&S.C->err, kErrTableFull);
+            } else {
+                Slot *sl = S.T + slot;
+                if (claimed) {
+                    fresh = true;
+                    const unsigned long long pool = atomicAdd(&S.C->pool_next, 1ull);
+                    if (int64_t(pool) < S.pool_cap) {
+                        S.pool_key[pool] = key;
+                        st_val(sl, int32_t(pool));
+                    } else {
+                        st_val(sl, kNoPool);
+                        raise_err(&S.C->err, kErrPoolFull);
+                    }
+                }
+                const uint32_t cur = __hip_atomic_load(&sl->stamp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (cur != frame) append = atomicMax(&sl->stamp, frame) < frame;
+            }
+        }
+        const unsigned int pos = wave_append<unsigned int>(append, &fc->n_touched);
+        if (append) S.touched[pos] = int32_t(slot);
+        const unsigned long long nm = __ballot(fresh);
+        if (nm && lane == __builtin_ctzll(nm)) atomicAdd(&fc->n_new, unsigned(__popcll(nm)));
+        prev = ok ? key : kEmpty;
+    }
+}
+
+// ----------------------------------------------------------------- integration
+// One wave per touched block; lane = lx + 8 ly handles voxels (lx, ly, lz), lz = 0..7.
+//   pw_i = (float)g_i * vs, dl_i = pw_i - t_i, pc_j = (R_0j dl_0 + R_1j dl_1) + R_2j dl_2;
+//   skip if pc_z <= 0; u = floor((fx (pc_x / pc_z) + cx) + 0.5) (same for v); skip if
+//   outside the image; skip unless the pixel depth d is valid; sdf = d - pc_z; skip if
+//   sdf < -mu.  Then F <- (W F + min(sdf, mu)) / (W + 1), W <- min(W + 1, 255) and each
+//   colour channel c <- (W c + c_obs + floor(n / 2)) / n with n = W + 1.
+__global__ void __launch_bounds__(kBlock) k_integrate(Dev S, Frame fr, const float *__restrict__ depth,
+                                                      const uint8_t *__restrict__ rgb, int seq) {
+    const FrameCounters *fc = &S.C->fc[seq & (kRing - 1)];
+    const int64_t n = fc->n_touched;
+    const int lane = lane_id();
+    const int lx = lane & 7, ly = lane >> 3;
+    const int64_t gw = int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6);
+    const int64_t nw = int64_t(gridDim.x) * kWaves;
+    unsigned long long updates = 0;
+    for (int64_t t = gw; t < n; t += nw) {
+        const Slot *sl = S.T + S.touched[t];
+        const int32_t pool = sl->val;
+        if (pool < 0) continue;
+        int32_t bx, by, bz;
+        unpack_key(sl->key, bx, by, bz);
+        const float dlx = float(8 * bx + lx) * fr.vs - fr.P[3];
+        const float dly = float(8 * by + ly) * fr.vs - fr.P[7];
+        const int64_t base = int64_t(pool) * 512 + lane;
+#pragma unroll 2
+        for (int j = 0; j < 8; ++j) {
+            const float dlz = float(8 * bz + j) * fr.vs - fr.P[11];
+            const float pcx = (fr.P[0] * dlx + fr.P[4] * dly) + fr.P[8] * dlz;
+            const float pcy = (fr.P[1] * dlx + fr.P[5] * dly) + fr.P[9] * dlz;
+            const float pcz = (fr.P[2] * dlx + fr.P[6] * dly) + fr.P[10] * dlz;
+            if (!(pcz > 0.0f)) continue;
+            const float fu = floorf((fr.fx * (pcx / pcz) + fr.cx) + 0.5f);
+            const float fv = floorf((fr.fy * (pcy / pcz) + fr.cy) + 0.5f);
+            if (!(fu >= 0.0f && fu < float(fr.W) && fv >= 0.0f && fv < float(fr.H))) continue;
+            const int64_t pix = int64_t(fv) * fr.W + int64_t(fu);
+            const float d = depth[pix];
+            if (!depth_valid(d, fr)) continue;
+            const float sdf = d - pcz;
+            if (sdf < -fr.mu) continue;
+            const float tsdf = fminf(sdf, fr.mu);
+            const int64_t idx = base + 64 * j;
+            const float F = S.F[idx];
+            const uint32_t w = S.WRGB[idx];
+            const uint32_t w_old = w & 0xFFu;
+            const uint32_t nn = w_old + 1u;
+            S.F[idx] = (float(w_old) * F + tsdf) / float(nn);
+            uint32_t out = nn > 255u ? 255u : nn;
+            if (rgb) {
+                const uint8_t *o = rgb + pix * 3;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const uint32_t cur = (w >> (8 * (c + 1))) & 0xFFu;
+                    out |= ((w_old * cur + uint32_t(o[c]) + (nn >> 1)) / nn) << (8 * (c + 1));
+                }
+            } else {
+                out |= w & 0xFFFFFF00u;
+            }
+            S.WRGB[idx] = out;
+            ++updates;
+        }
+    }
+    updates = wave_sum(updates);
+    if (lane == 0 && updates) atomicAdd((unsigned long long *)&S.C->fc[seq & (kRing - 1)].voxel_updates, updates);
+}
+
+// ---------------------------------------------------------------- MC update set
+// Thread per (touched block, e in {0,1}^3): block B - e, if it exists, joins the frame's
+// MC update set (the touched blocks and their seven negative neighbours).  The first
+// thread to raise its MC stamp appends it to the MC list and to the update log.
+__device__ __forceinline__ void mark_one(const Dev &S, int32_t target, uint32_t frame, FrameCounters *fc, bool active) {
+    bool mark = false;
+    if (active && target >= 0) {
+        const uint32_t cur = __hip_atomic_load(&S.mc_stamp[target], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (cur != frame) mark = atomicMax(&S.mc_stamp[target], frame) < frame;
+    }
+    const unsigned int pos = wave_append<unsigned int>(mark, &fc->n_mc);
+    const unsigned long long lpos = wave_append<unsigned long long>(mark, &S.C->log_len);
+    if (mark) {
+        S.mclist[pos] = target;
+        if (lpos < S.log_cap)
+            S.log[lpos] = (uint64_t(frame) << 32) | uint32_t(target);
+        else
+            raise_err(&S.C->err, kErrLogFull);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_mc_mark(Dev S, uint32_t frame, int seq) {
+    FrameCounters *fc = &S.C->fc[seq & (kRing - 1)];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        S.C->tot_touched += fc->n_touched;
+        S.C->tot_voxel_updates += fc->voxel_updates;
+    }
+    const int64_t total = int64_t(fc->n_touched) * 8;
+    const int lane = lane_id();
+    const int64_t stride = int64_t(gridDim.x) * kBlock;
+    for (int64_t b = int64_t(blockIdx.x) * kBlock + (threadIdx.x & ~63); b < total; b += stride) {
+        const int64_t i = b + lane;
+        const bool active = i < total;
+        int32_t target = -1;
+        if (active) {
+            const Slot *sl = S.T + S.touched[i >> 3];
+            const int32_t pool = sl->val;
+            const int e = int(i & 7);
+            if (pool >= 0) {
+                if (e == 0) {
+                    target = pool;
+                } else {
+                    int32_t bx, by, bz;
+                    unpack_key(sl->key, bx, by, bz);
+                    const int32_t nx = bx - (e & 1), ny = by - ((e >> 1) & 1), nz = bz - ((e >> 2) & 1);
+                    if (key_ok(nx, ny, nz)) {
+                        const uint64_t nk = pack_key(nx, ny, nz);
+                        const int64_t ps = probe_locate(S.T, S.mask, nk, home_slot(nx, ny, nz, nk, S.kind, S.mask));
+                        if (ps >= 0) target = S.T[ps].val;
+                    }
+                }
+            }
+        }
+        mark_one(S, target, frame, fc, active);
+    }
+}
+
+// ------------------------------------------------------------- MC extraction
+// One wave per block.  The block and its +x/+y/+z halo (9^3 F values, NaN where W = 0 or
+// the neighbour block is missing) are staged in LDS; each lane then forms the case
+// index of voxels (lx, ly, 0..7) from its 8 corners in Lorensen-Cline order, bit k set
+// iff F(corner k) < 0, index 0 if any corner is NaN, and indices 0 / 255 cut to 0.
+constexpr int kHalo = 729;
+
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ float halo_value(const Dev &S, int32_t pool, int l) {
+    if (pool < 0) return __builtin_nanf("");
+    const int64_t idx = int64_t(pool) * 512 + l;
+    const uint32_t w = S.WRGB[idx];
+    return (w & 0xFFu) ? S.F[idx] : __builtin_nanf("");
+}
+
+// Computes the 512 MC voxels of block `pool` (key B) into out[j] for voxel lane + 64 j.
+__device__ __forceinline__ void mc_block(const Dev &S, int32_t pool, uint64_t key, float *halo, uint32_t (&out)[8]) {
+    const int lane = lane_id();
+    int32_t bx, by, bz;
+    unpack_key(key, bx, by, bz);
+    int32_t nb = -1;
+    if (lane < 8) {
+        if (lane == 0) {
+            nb = pool;
+        } else {
+            const int32_t nx = bx + (lane & 1), ny = by + ((lane >> 1) & 1), nz = bz + ((lane >> 2) & 1);
+            if (key_ok(nx, ny, nz)) {
+                const uint64_t nk = pack_key(nx, ny, nz);
+                const int64_t ps = probe_locate(S.T, S.mask, nk, home_slot(nx, ny, nz, nk, S.kind, S.mask));
+                if (ps >= 0) nb = S.T[ps].val;
+            }
+        }
+    }
+    int32_t nbs[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) nbs[e] = __shfl(nb, e);
+    uint32_t own[8];
+    const int lx = lane & 7, ly = lane >> 3;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int64_t idx = int64_t(pool) * 512 + lane + 64 * j;
+        const uint32_t w = S.WRGB[idx];
+        own[j] = w;
+        halo[lx + 9 * ly + 81 * j] = (w & 0xFFu) ? S.F[idx] : __builtin_nanf("");
+    }
+    // faces: x = 8 from block +x (local x = 0), y = 8 from +y, z = 8 from +z
+    {
+        const int a = lane & 7, b = lane >> 3;
+        halo[8 + 9 * a + 81 * b] = halo_value(S, nbs[1], 0 + 8 * a + 64 * b);
+        halo[a + 9 * 8 + 81 * b] = halo_value(S, nbs[2], a + 0 + 64 * b);
+        halo[a + 9 * b + 81 * 8] = halo_value(S, nbs[4], a + 8 * b + 0);
+    }
+    // edges and the corner
+    if (lane < 8) {
+        halo[8 + 9 * 8 + 81 * lane] = halo_value(S, nbs[3], 0 + 0 + 64 * lane);      // +x+y
+    } else if (lane < 16) {
+        const int a = lane - 8;
+        halo[8 + 9 * a + 81 * 8] = halo_value(S, nbs[5], 0 + 8 * a + 0);            // +x+z
+    } else if (lane < 24) {
+        const int a = lane - 16;
+        halo[a + 9 * 8 + 81 * 8] = halo_value(S, nbs[6], a + 0 + 0);                // +y+z
+    } else if (lane == 24) {
+        halo[8 + 9 * 8 + 81 * 8] = halo_value(S, nbs[7], 0);                        // +x+y+z
+    }
+    wave_sync_lds();
+    constexpr int off[8] = {0, 1, 10, 9, 81, 82, 91, 90};
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int base = lx + 9 * ly + 81 * j;
+        uint32_t idx = 0;
+        bool bad = false;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const float c = halo[base + off[k]];
+            bad |= c != c;
+            idx |= uint32_t(c < 0.0f) << k;
+        }
+        if (bad || idx == 0u || idx == 255u)
+            out[j] = 0u;
+        else
+            out[j] = idx | (own[j] & 0xFFFFFF00u);
+    }
+    wave_sync_lds();  // halo is reused by the next block of this wave
+}
+
+// Per-frame form: MC list -> MC pool.
+__global__ void __launch_bounds__(kBlock) k_mc_extract(Dev S, int seq) {
+    __shared__ float halo_all[kWaves][kHalo];
+    float *halo = halo_all[threadIdx.x >> 6];
+    const int64_t n = S.C->fc[seq & (kRing - 1)].n_mc;
+    if (blockIdx.x == 0 && threadIdx.x == 0) S.C->tot_mc += n;
+    const int lane = lane_id();
+    const int64_t gw = int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6);
+    const int64_t nw = int64_t(gridDim.x) * kWaves;
+    for (int64_t t = gw; t < n; t += nw) {
+        const int32_t pool = S.mclist[t];
+        uint32_t out[8];
+        mc_block(S, pool, S.pool_key[pool], halo, out);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) S.MCV[int64_t(pool) * 512 + lane + 64 * j] = out[j];
+    }
+}
+
+// API form: keys -> uint8 index [n][512] and optional uint8 RGB [n][512][3].
+__global__ void __launch_bounds__(kBlock) k_mc_keys(Dev S, const int32_t *__restrict__ keys, int64_t n, uint8_t *mc,
+                                                    uint8_t *rgb) {
+    __shared__ float halo_all[kWaves][kHalo];
+    float *halo = halo_all[threadIdx.x >> 6];
+    const int lane = lane_id();
+    const int64_t gw = int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6);
+    const int64_t nw = int64_t(gridDim.x) * kWaves;
+    for (int64_t t = gw; t < n; t += nw) {
+        const int32_t x = keys[3 * t], y = keys[3 * t + 1], z = keys[3 * t + 2];
+        int32_t pool = -1;
+        if (key_ok(x, y, z)) {
+            const uint64_t k = pack_key(x, y, z);
+            const int64_t ps = probe_locate(S.T, S.mask, k, home_slot(x, y, z, k, S.kind, S.mask));
+            if (ps >= 0) pool = S.T[ps].val;
+        }
+        uint32_t out[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (pool >= 0) mc_block(S, pool, pack_key(x, y, z), halo, out);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int64_t o = t * 512 + lane + 64 * j;
+            mc[o] = uint8_t(out[j]);
+            if (rgb) {
+                rgb[3 * o] = uint8_t(out[j] >> 8);
+                rgb[3 * o + 1] = uint8_t(out[j] >> 16);
+                rgb[3 * o + 2] = uint8_t(out[j] >> 24);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- block I/O
+__device__ __forceinline__ int32_t lookup_pool(const Dev &S, int32_t x, int32_t y, int32_t z) {
+    if (!key_ok(x, y, z)) return -1;
+    const uint64_t k = pack_key(x, y, z);
+    const int64_t ps = probe_locate(S.T, S.mask, k, home_slot(x, y, z, k, S.kind, S.mask));
+    return ps >= 0 ? S.T[ps].val : -1;
+}
+
+__global__ void __launch_bounds__(kBlock) k_read_blocks(Dev S, const int32_t *keys, int64_t n, float *F, uint8_t *W,
+                                                        uint8_t *rgb, int32_t *found, int mcmode) {
+    const int lane = lane_id();
+    const int64_t gw = int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6);
+    const int64_t nw = int64_t(gridDim.x) * kWaves;
+    for (int64_t t = gw; t < n; t += nw) {
+        const int32_t pool = lookup_pool(S, keys[3 * t], keys[3 * t + 1], keys[3 * t + 2]);
+        if (found && lane == 0) found[t] = pool >= 0;
+        for (int j = 0; j < 8; ++j) {
+            const int64_t o = t * 512 + lane + 64 * j;
+            const int64_t src = int64_t(pool) * 512 + lane + 64 * j;
+            const uint32_t w = pool >= 0 ? (mcmode ? S.MCV[src] : S.WRGB[src]) : 0u;
+            if (F) F[o] = pool >= 0 ? S.F[src] : 0.0f;
+            if (W) W[o] = uint8_t(w);
+            if (rgb) {
+                rgb[3 * o] = uint8_t(w >> 8);
+                rgb[3 * o + 1] = uint8_t(w >> 16);
+                rgb[3 * o + 2] = uint8_t(w >> 24);
+            }
+        }
+    }
+}
+
+// Thread per key: insert (allocating a pool block), stamp as touched by `frame`.
+__global__ void __launch_bounds__(kBlock) k_load_claim(Dev S, const int32_t *keys, int64_t n, uint32_t frame, int seq) {
+    FrameCounters *fc = &S.C->fc[seq & (kRing - 1)];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        FrameCounters z = {};
+        S.C->fc[(seq + 2) & (kRing - 1)] = z;
+    }
+    const int64_t stride = int64_t(gridDim.x) * kBlock;
+    for (int64_t b = int64_t(blockIdx.x) * kBlock + (threadIdx.x & ~63); b < n; b += stride) {
+        const int64_t i = b + lane_id();
+        bool append = false, fresh = false;
+        int64_t slot = -1;
+        if (i < n) {
+            const int32_t x = keys[3 * i], y = keys[3 * i + 1], z = keys[3 * i + 2];
+            if (!key_ok(x, y, z)) {
+                raise_err(&S.C->err, kErrKeyRange);
+            } else {
+                const uint64_t key = pack_key(x, y, z);
+                bool claimed;
+                slot = probe_claim(S.T, S.mask, key, home_slot(x, y, z, key, S.kind, S.mask), claimed);
+                if (slot < 0) {
+                    raise_err(&S.C->err, kErrTableFull);
+                } else {
+                    Slot *sl = S.T + slot;
+                    if (claimed) {
+                        fresh = true;
+                        const unsigned long long pool = atomicAdd(&S.C->pool_next, 1ull);
+                        if (int64_t(pool) < S.pool_cap) {
+                            S.pool_key[pool] = key;
+                            st_val(sl, int32_t(pool));
+                        } else {
+                            st_val(sl, kNoPool);
+                            raise_err(&S.C->err, kErrPoolFull);
+                        }
+                    }
+                    append = atomicMax(&sl->stamp, frame) < frame;
+                }
+            }
+        }
+        const unsigned int pos = wave_append<unsigned int>(append, &fc->n_touched);
+        if (append) S.touched[pos] = int32_t(slot);
+        const unsigned long long nm = __ballot(fresh);
+        if (nm && lane_id() == __builtin_ctzll(nm)) atomicAdd(&fc->n_new, unsigned(__popcll(nm)));
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_load_copy(Dev S, const int32_t *keys, int64_t n, const float *F,
+                                                      const uint8_t *W, const uint8_t *rgb) {
+    const int lane = lane_id();
+    const int64_t gw = int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6);
+    const int64_t nw = int64_t(gridDim.x) * kWaves;
+    for (int64_t t = gw; t < n; t += nw) {
+        const int32_t pool = lookup_pool(S, keys[3 * t], keys[3 * t + 1], keys[3 * t + 2]);
+        if (pool < 0) continue;
+        for (int j = 0; j < 8; ++j) {
+            const int64_t i = t * 512 + lane + 64 * j;
+            const int64_t o = int64_t(pool) * 512 + lane + 64 * j;
+            uint32_t w = W[i];
+            if (rgb) w |= uint32_t(rgb[3 * i]) << 8 | uint32_t(rgb[3 * i + 1]) << 16 | uint32_t(rgb[3 * i + 2]) << 24;
+            S.F[o] = F[i];
+            S.WRGB[o] = w;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_keys_of(Dev S, int which, int seq, int64_t cap, int32_t *out) {
+    // which: 0 = pool order (all blocks), 1 = last touched list, 2 = last MC list
+    int64_t n;
+    if (which == 0) {
+        const unsigned long long pn = S.C->pool_next;
+        n = int64_t(pn) < S.pool_cap ? int64_t(pn) : S.pool_cap;
+    } else {
+        const FrameCounters &fc = S.C->fc[seq & (kRing - 1)];
+        n = which == 1 ? fc.n_touched : fc.n_mc;
+    }
+    if (n > cap) n = cap;
+    for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock) {
+        uint64_t key;
+        if (which == 0) key = S.pool_key[i];
+        else if (which == 1) key = S.T[S.touched[i]].key;
+        else key = S.pool_key[S.mclist[i]];
+        int32_t x, y, z;
+        unpack_key(key, x, y, z);
+        out[3 * i] = x;
+        out[3 * i + 1] = y;
+        out[3 * i + 2] = z;
+    }
+}
+
+// ------------------------------------------------------------ paged log walk
+// Entry (f, b) is live iff mc_stamp[b] == f (the block's latest MC update).  Chunks of
+// kChunk entries are counted (k_log_count), scanned (k_log_scan, one workgroup) and
+// emitted in log order (k_log_emit) up to `cap` keys.
+__device__ __forceinline__ uint64_t log_end(const Dev &S) {
+    const unsigned long long L = S.C->log_len;
+    return L < S.log_cap ? L : S.log_cap;
+}
+
+__device__ __forceinline__ bool log_live(const Dev &S, uint64_t pos, uint64_t end) {
+    if (pos >= end) return false;
+    const uint64_t e = S.log[pos];
+    return S.mc_stamp[uint32_t(e)] == uint32_t(e >> 32);
+}
+
+__global__ void __launch_bounds__(kBlock) k_log_count(Dev S, uint64_t cursor) {
+    __shared__ int part[kWaves];
+    const uint64_t end = log_end(S);
+    const int64_t nch = cursor < end ? int64_t((end - cursor + kChunk - 1) / kChunk) : 0;
+    for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
+        int cnt = 0;
+        for (int k = 0; k < kChunk / kBlock; ++k)
+            cnt += log_live(S, cursor + uint64_t(c) * kChunk + uint64_t(k) * kBlock + threadIdx.x, end);
+        cnt = wave_sum(cnt);
+        if (lane_id() == 0) part[threadIdx.x >> 6] = cnt;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int s = 0;
+            for (int w = 0; w < kWaves; ++w) s += part[w];
+            S.prefix[c] = s;
+        }
+        __syncthreads();
+    }
+}
+
+constexpr int kScan = 1024;
+__global__ void __launch_bounds__(kScan) k_log_scan(Dev S, uint64_t cursor, int64_t cap, int64_t *d_count,
+                                                    uint64_t *d_next) {
+    __shared__ int64_t part[kScan];
+    const uint64_t end = log_end(S);
+    const int64_t nch = cursor < end ? int64_t((end - cursor + kChunk - 1) / kChunk) : 0;
+    const int64_t per = (nch + kScan - 1) / kScan;
+    const int64_t lo = threadIdx.x * per, hi = lo + per < nch ? lo + per : nch;
+    int64_t s = 0;
+    for (int64_t c = lo; c < hi; ++c) s += S.prefix[c];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 1; o < kScan; o <<= 1) {  // inclusive Hillis-Steele scan
+        const int64_t v = threadIdx.x >= o ? part[threadIdx.x - o] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int64_t run = part[threadIdx.x] - s;  // exclusive prefix of this thread's range
+    for (int64_t c = lo; c < hi; ++c) {
+        const int64_t v = S.prefix[c];
+        S.prefix[c] = run;
+        run += v;
+    }
+    if (threadIdx.x == kScan - 1) {
+        const int64_t total = part[kScan - 1];
+        const int64_t cnt = total < cap ? total : cap;
+        *d_count = cnt;
+        if (cap == 0)
+            *d_next = cursor;
+        else if (total < cap)
+            *d_next = end;
+        // otherwise k_log_emit writes the position after the cap-th live entry
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_log_emit(Dev S, uint64_t cursor, int64_t cap, int32_t *keys,
+                                                     uint64_t *d_next) {
+    __shared__ int wcount[kWaves];
+    const uint64_t end = log_end(S);
+    const int64_t nch = cursor < end ? int64_t((end - cursor + kChunk - 1) / kChunk) : 0;
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
+        int64_t rank = S.prefix[c];
+        if (rank >= cap) continue;  // uniform per workgroup
+        for (int k = 0; k < kChunk / kBlock; ++k) {
+            const uint64_t pos = cursor + uint64_t(c) * kChunk + uint64_t(k) * kBlock + threadIdx.x;
+            const bool live = log_live(S, pos, end);
+            const unsigned long long m = __ballot(live);
+            if (lane == 0) wcount[wave] = __popcll(m);
+            __syncthreads();
+            int64_t before = rank;
+            int64_t total = 0;
+            for (int w = 0; w < kWaves; ++w) {
+                if (w < wave) before += wcount[w];
+                total += wcount[w];
+            }
+            const int64_t r = before + lanes_below(m);
+            if (live && r < cap) {
+                int32_t x, y, z;
+                unpack_key(S.pool_key[uint32_t(S.log[pos])], x, y, z);
+                keys[3 * r] = x;
+                keys[3 * r + 1] = y;
+                keys[3 * r + 2] = z;
+                if (r == cap - 1) *d_next = pos + 1;
+            }
+            rank += total;
+            __syncthreads();
+        }
+    }
+}
+
+__global__ void k_read_counters(const Counters *C, int seq, unsigned long long *out) {
+    const FrameCounters &fc = C->fc[seq & (kRing - 1)];
+    out[7] = C->tot_touched;
+    out[8] = C->tot_mc;
+    out[9] = C->tot_voxel_updates;
+    out[0] = fc.n_touched;
+    out[1] = fc.n_new;
+    out[2] = fc.n_mc;
+    out[3] = fc.voxel_updates;
+    out[4] = C->pool_next;
+    out[5] = C->log_len;
+    out[6] = C->err;
+}
+
+__global__ void k_clear_err(Counters *C) { C->err = 0; }
+
+}  // namespace
+
+// ======================================================================= host side
+struct vbh_scene {
+    vbh_params p{};
+    int m_band = 0;
+    Dev d{};
+    Counters *C = nullptr;
+    unsigned long long *hostbuf = nullptr;  // device staging for counters
+    int64_t max_chunks = 0;
+    int seq = 0;        // number of updates so far (ring index of the next one)
+    int cus = 256;      // compute units of the device the scene lives on
+    uint32_t last_frame = 0;
+    void *mem[12] = {};
+    bool timing = false;
+    std::vector<std::array<hipEvent_t, 5>> ev_pending, ev_free;
+};
+
+namespace {
+
+Frame make_frame(const vbh_scene *s, const float *pose) {
+    Frame f;
+    std::memcpy(f.P, pose, sizeof(f.P));
+    f.fx = s->p.fx;
+    f.fy = s->p.fy;
+    f.cx = s->p.cx;
+    f.cy = s->p.cy;
+    f.W = s->p.width;
+    f.H = s->p.height;
+    f.dmin = s->p.depth_min;
+    f.dmax = s->p.depth_max;
+    f.vs = s->p.voxel_size;
+    f.mu = s->p.trunc;
+    f.m_band = s->m_band;
+    return f;
+}
+
+unsigned wave_grid(const vbh_scene *s, int64_t cap_items) {
+    // waves-per-item kernels: enough workgroups to fill every CU several times over
+    const int64_t want = int64_t(s->cus) * 8;
+    const int64_t need = (cap_items + kWaves - 1) / kWaves;
+    return unsigned(need < want ? (need > 0 ? need : 1) : want);
+}
+
+// Runs the MC update for the blocks in the touched list of update `seq`.
+int mc_update(vbh_scene *s, uint32_t frame, int seq, hipStream_t st) {
+    const unsigned g = unsigned(s->cus) * 8;
+    k_mc_mark<<<g, kBlock, 0, st>>>(s->d, frame, seq);
+    k_mc_extract<<<g, kBlock, 0, st>>>(s->d, seq);
+    VBH_LAUNCHED();
+    return VBH_OK;
+}
+
+int read_counters(vbh_scene *s, int seq, unsigned long long (&h)[10], hipStream_t st) {
+    k_read_counters<<<1, 1, 0, st>>>(s->C, seq, s->hostbuf);
+    VBH_LAUNCHED();
+    VBH_HIP(hipMemcpyAsync(h, s->hostbuf, sizeof(h), hipMemcpyDeviceToHost, st));
+    VBH_HIP(hipStreamSynchronize(st));
+    return VBH_OK;
+}
+
+int keys_of(vbh_scene *s, int which, int32_t *d_keys, int64_t cap, int64_t *h_count, void *stream) {
+    if (!s || cap < 0 || (cap > 0 && !d_keys)) return VBH_EINVAL;
+    hipStream_t st = as_stream(stream);
+    unsigned long long h[10];
+    const int seq = s->seq - 1;
+    if (int rc = read_counters(s, seq < 0 ? 0 : seq, h, st)) return rc;
+    int64_t n;
+    if (which == 0) n = int64_t(h[4]) < s->p.pool_blocks ? int64_t(h[4]) : s->p.pool_blocks;
+    else n = s->seq == 0 ? 0 : int64_t(which == 1 ? h[0] : h[2]);
+    if (h_count) *h_count = n;
+    const int64_t m = n < cap ? n : cap;
+    if (m > 0) {
+        k_keys_of<<<grid_for(m, kBlock, 4096), kBlock, 0, st>>>(s->d, which, seq < 0 ? 0 : seq, cap, d_keys);
+        VBH_LAUNCHED();
+        VBH_HIP(hipStreamSynchronize(st));
+    }
+    return VBH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vbh_scene_create(const vbh_params *p, vbh_scene **out) {
+    if (!out || !p) return VBH_EINVAL;
+    *out = nullptr;
+    if (!is_pow2(p->slots) || p->slots < 64 || p->slots > (1ull << 31) || p->pool_blocks < 1 ||
+        p->pool_blocks > (int64_t(1) << 30) || p->log_capacity < 1 || !(p->voxel_size > 0) ||
+        !(p->trunc >= p->voxel_size) || p->width <= 0 || p->height <= 0 || !(p->fx > 0) || !(p->fy > 0) ||
+        p->hash_kind < 0 || p->hash_kind > 1 || !(p->depth_max >= p->depth_min))
+        return VBH_EINVAL;
+    vbh_scene *s = new (std::nothrow) vbh_scene();
+    if (!s) return VBH_ENOMEM;
+    s->p = *p;
+    s->m_band = int(floorf(p->trunc / p->voxel_size + 0.5f));
+    s->cus = vbh::device_cus();
+    const uint64_t P = uint64_t(p->pool_blocks);
+    s->max_chunks = (p->log_capacity + kChunk - 1) / kChunk + 1;
+    const size_t sizes[] = {p->slots * sizeof(Slot), P * 512 * sizeof(float), P * 512 * 4, P * 512 * 4,
+                            P * 8,                  P * 4,                     p->slots * 4, P * 4,
+                            size_t(p->log_capacity) * 8, size_t(s->max_chunks) * 8, sizeof(Counters), 64 * 8};
+    for (int i = 0; i < 12; ++i) {
+        if (hipMalloc(&s->mem[i], sizes[i]) != hipSuccess) {
+            vbh_scene_destroy(s);
+            return VBH_ENOMEM;
+        }
+    }
+    Dev &d = s->d;
+    d.T = static_cast<Slot *>(s->mem[0]);
+    d.mask = p->slots - 1;
+    d.kind = p->hash_kind;
+    d.F = static_cast<float *>(s->mem[1]);
+    d.WRGB = static_cast<uint32_t *>(s->mem[2]);
+    d.MCV = static_cast<uint32_t *>(s->mem[3]);
+    d.pool_key = static_cast<uint64_t *>(s->mem[4]);
+    d.mc_stamp = static_cast<uint32_t *>(s->mem[5]);
+    d.touched = static_cast<int32_t *>(s->mem[6]);
+    d.mclist = static_cast<int32_t *>(s->mem[7]);
+    d.log = static_cast<uint64_t *>(s->mem[8]);
+    d.prefix = static_cast<int64_t *>(s->mem[9]);
+    d.pool_cap = p->pool_blocks;
+    d.log_cap = uint64_t(p->log_capacity);
+    s->C = static_cast<Counters *>(s->mem[10]);
+    d.C = s->C;
+    s->hostbuf = static_cast<unsigned long long *>(s->mem[11]);
+    bool ok = vbh::table_init(d.T, p->slots, nullptr) == VBH_OK;
+    for (int i = 1; i <= 5 && ok; ++i) ok = hipMemset(s->mem[i], 0, sizes[i]) == hipSuccess;
+    ok = ok && hipMemset(s->C, 0, sizeof(Counters)) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+    if (!ok) {
+        vbh_scene_destroy(s);
+        return VBH_EHIP;
+    }
+    *out = s;
+    return VBH_OK;
+}
+
+void vbh_scene_destroy(vbh_scene *s) {
+    if (!s) return;
+    for (auto *v : {&s->ev_pending, &s->ev_free})
+        for (auto &ev : *v)
+            for (auto e : ev) (void)hipEventDestroy(e);
+    for (void *m : s->mem)
+        if (m) (void)hipFree(m);
+    delete s;
+}
+
+int vbh_integrate_frame(vbh_scene *s, const float *d_depth, const uint8_t *d_rgb, const float *pose_c2w,
+                        uint32_t frame_id, void *stream) {
+    if (!s || !d_depth || !pose_c2w || frame_id == 0 || frame_id <= s->last_frame) return VBH_EINVAL;
+    for (int i = 0; i < 12; ++i)
+        if (!std::isfinite(pose_c2w[i])) return VBH_EINVAL;
+    hipStream_t st = as_stream(stream);
+    const Frame fr = make_frame(s, pose_c2w);
+    const int seq = s->seq;
+    std::array<hipEvent_t, 5> ev{};
+    if (s->timing) {
+        if (s->ev_free.empty()) {
+            for (auto &e : ev) VBH_HIP(hipEventCreate(&e));
+        } else {
+            ev = s->ev_free.back();
+            s->ev_free.pop_back();
+        }
+        s->ev_pending.push_back(ev);
+    }
+    auto mark = [&](int i) { return s->timing ? hipEventRecord(ev[i], st) : hipSuccess; };
+    dim3 ga(unsigned((s->p.width + 15) / 16), unsigned((s->p.height + 15) / 16));
+    const unsigned g = unsigned(s->cus) * 8;
+    VBH_HIP(mark(0));
+    k_alloc<<<ga, kBlock, 0, st>>>(s->d, fr, d_depth, frame_id, seq);
+    VBH_HIP(mark(1));
+    k_integrate<<<g, kBlock, 0, st>>>(s->d, fr, d_depth, d_rgb, seq);
+    VBH_HIP(mark(2));
+    k_mc_mark<<<g, kBlock, 0, st>>>(s->d, frame_id, seq);
+    VBH_HIP(mark(3));
+    k_mc_extract<<<g, kBlock, 0, st>>>(s->d, seq);
+    VBH_HIP(mark(4));
+    VBH_LAUNCHED();
+    s->seq = seq + 1;
+    s->last_frame = frame_id;
+    return VBH_OK;
+}
+
+int vbh_extract_mc_indices(vbh_scene *s, const int32_t *d_keys, int64_t n, uint8_t *d_mc, uint8_t *d_rgb,
+                           void *stream) {
+    if (!s || n < 0 || (n > 0 && (!d_keys || !d_mc))) return VBH_EINVAL;
+    if (n == 0) return VBH_OK;
+    k_mc_keys<<<wave_grid(s, n), kBlock, 0, as_stream(stream)>>>(s->d, d_keys, n, d_mc, d_rgb);
+    VBH_LAUNCHED();
+    return VBH_OK;
+}
+
+int vbh_stored_mc(vbh_scene *s, const int32_t *d_keys, int64_t n, uint8_t *d_mc, uint8_t *d_rgb, void *stream) {
+    if (!s || n < 0 || (n > 0 && (!d_keys || !d_mc))) return VBH_EINVAL;
+    if (n == 0) return VBH_OK;
+    k_read_blocks<<<wave_grid(s, n), kBlock, 0, as_stream(stream)>>>(s->d, d_keys, n, nullptr, d_mc, d_rgb, nullptr, 1);
+    VBH_LAUNCHED();
+    return VBH_OK;
+}
+
+int vbh_updated_blocks_since(vbh_scene *s, uint64_t cursor, int64_t cap, int32_t *d_keys_out, int64_t *d_count,
+                             uint64_t *d_next_cursor, void *stream) {
+    if (!s || cap < 0 || !d_count || !d_next_cursor || (cap > 0 && !d_keys_out)) return VBH_EINVAL;
+    hipStream_t st = as_stream(stream);
+    const unsigned g = unsigned(s->cus) * 4;
+    k_log_count<<<g, kBlock, 0, st>>>(s->d, cursor);
+    k_log_scan<<<1, kScan, 0, st>>>(s->d, cursor, cap, d_count, d_next_cursor);
+    if (cap > 0) k_log_emit<<<g, kBlock, 0, st>>>(s->d, cursor, cap, d_keys_out, d_next_cursor);
+    VBH_LAUNCHED();
+    return VBH_OK;
+}
+
+int vbh_scene_status(vbh_scene *s, void *stream) {
+    if (!s) return VBH_EINVAL;
+    hipStream_t st = as_stream(stream);
+    unsigned long long h[10];
+    if (int rc = read_counters(s, s->seq > 0 ? s->seq - 1 : 0, h, st)) return rc;
+    if (h[6]) {
+        k_clear_err<<<1, 1, 0, st>>>(s->C);
+        VBH_LAUNCHED();
+        VBH_HIP(hipStreamSynchronize(st));
+    }
+    return code_from_bits(uint32_t(h[6]));
+}
+
+int vbh_scene_stats(vbh_scene *s, vbh_stats *o, void *stream) {
+    if (!s || !o) return VBH_EINVAL;
+    unsigned long long h[10];
+    if (int rc = read_counters(s, s->seq > 0 ? s->seq - 1 : 0, h, as_stream(stream))) return rc;
+    const bool any = s->seq > 0;
+    o->n_touched = any ? int64_t(h[0]) : 0;
+    o->n_new = any ? int64_t(h[1]) : 0;
+    o->n_mc = any ? int64_t(h[2]) : 0;
+    o->n_voxel_updates = any ? int64_t(h[3]) : 0;
+    o->n_blocks = int64_t(h[4]) < s->p.pool_blocks ? int64_t(h[4]) : s->p.pool_blocks;
+    o->log_length = h[5] < uint64_t(s->p.log_capacity) ? h[5] : uint64_t(s->p.log_capacity);
+    o->last_frame = s->last_frame;
+    o->error = code_from_bits(uint32_t(h[6]));
+    o->total_touched = int64_t(h[7]);
+    o->total_mc = int64_t(h[8]);
+    o->total_voxel_updates = int64_t(h[9]);
+    return VBH_OK;
+}
+
+int vbh_scene_export_blocks(vbh_scene *s, int32_t *d_keys, int64_t cap, int64_t *h_count, void *stream) {
+    return keys_of(s, 0, d_keys, cap, h_count, stream);
+}
+int vbh_scene_last_touched(vbh_scene *s, int32_t *d_keys, int64_t cap, int64_t *h_count, void *stream) {
+    return keys_of(s, 1, d_keys, cap, h_count, stream);
+}
+int vbh_scene_last_mc(vbh_scene *s, int32_t *d_keys, int64_t cap, int64_t *h_count, void *stream) {
+    return keys_of(s, 2, d_keys, cap, h_count, stream);
+}
+
+int vbh_scene_read_blocks(vbh_scene *s, const int32_t *d_keys, int64_t n, float *d_F, uint8_t *d_W, uint8_t *d_rgb,
+                          int32_t *d_found, void *stream) {
+    if (!s || n < 0 || (n > 0 && !d_keys)) return VBH_EINVAL;
+    if (n == 0) return VBH_OK;
+    k_read_blocks<<<wave_grid(s, n), kBlock, 0, as_stream(stream)>>>(s->d, d_keys, n, d_F, d_W, d_rgb, d_found, 0);
+    VBH_LAUNCHED();
+    return VBH_OK;
+}
+
+int vbh_scene_write_blocks(vbh_scene *s, const int32_t *d_keys, int64_t n, const float *d_F, const uint8_t *d_W,
+                           const uint8_t *d_rgb, uint32_t frame_id, void *stream) {
+    if (!s || n < 0 || (n > 0 && (!d_keys || !d_F || !d_W)) || frame_id == 0 || frame_id <= s->last_frame)
+        return VBH_EINVAL;
+    hipStream_t st = as_stream(stream);
+    const int seq = s->seq;
+    k_load_claim<<<grid_for(n, kBlock, 8192), kBlock, 0, st>>>(s->d, d_keys, n, frame_id, seq);
+    if (n > 0) k_load_copy<<<wave_grid(s, n), kBlock, 0, st>>>(s->d, d_keys, n, d_F, d_W, d_rgb);
+    VBH_LAUNCHED();
+    if (int rc = mc_update(s, frame_id, seq, st)) return rc;
+    s->seq = seq + 1;
+    s->last_frame = frame_id;
+    return VBH_OK;
+}
+
+int vbh_scene_enable_timing(vbh_scene *s, int32_t enable) {
+    if (!s) return VBH_EINVAL;
+    s->timing = enable != 0;
+    return VBH_OK;
+}
+
+int vbh_scene_timing(vbh_scene *s, double *ms_out, int64_t *h_frames, void *stream) {
+    if (!s || !ms_out) return VBH_EINVAL;
+    VBH_HIP(hipStreamSynchronize(as_stream(stream)));
+    for (int i = 0; i < 4; ++i) ms_out[i] = 0.0;
+    for (auto &ev : s->ev_pending) {
+        for (int i = 0; i < 4; ++i) {
+            float ms = 0.0f;
+            VBH_HIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+            ms_out[i] += ms;
+        }
+        s->ev_free.push_back(ev);
+    }
+    if (h_frames) *h_frames = int64_t(s->ev_pending.size());
+    s->ev_pending.clear();
+    return VBH_OK;
+}
+
+}  // extern "C"

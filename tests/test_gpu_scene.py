@@ -1,0 +1,198 @@
+"""GPU parity of allocation, integration, MC voxels and the update log against the oracle.
+
+Bar: key sets, allocation sets, W and colour bit-exact; F within 1e-5 m of the float64
+oracle; MC voxels bit-exact on identical F/W input, and end to end only where some
+corner has |F_oracle| <= 1e-5.
+"""
+import numpy as np
+import pytest
+import torch
+
+from datagen import configs
+from gpu_util import keyset, require_gpu, say, sort_keys, to_dev
+
+pytestmark = pytest.mark.gpu
+F_TOL = 1e-5
+OFFS = np.array([(0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0), (0, 0, 1), (1, 0, 1), (1, 1, 1), (0, 1, 1)])
+
+
+def pose_np(p):
+    return np.asarray(p, np.float64).reshape(3, 4)
+
+
+def make_pair(vbh, orc, vol, cam, hash_kind=0):
+    return vbh.Scene(vbh.make_params(vol, cam, hash_kind)), orc.Scene(vol, cam)
+
+
+def integrate_both(G, O, depth, rgb, poses, frames, first_id=1, check_frames=True):
+    for i, f in enumerate(frames):
+        fid = first_id + i
+        d, c = depth[f], rgb[f]
+        G.vbh_integrate_frame(to_dev(d.numpy() if torch.is_tensor(d) else d),
+                              to_dev(c.numpy() if torch.is_tensor(c) else c), poses[f], fid)
+        rc = O.integrate(d.numpy() if torch.is_tensor(d) else d, c.numpy() if torch.is_tensor(c) else c,
+                         poses[f], fid)
+        assert rc == 0
+        if check_frames:
+            st = G.vbh_scene_stats()
+            gt = keyset(G.vbh_scene_last_touched())
+            ot = keyset(O.last_touched())
+            say(f"  frame {fid}: touched {len(gt)} new {st['n_new']} mc {st['n_mc']}")
+            assert gt == ot, (len(gt), len(ot), len(gt ^ ot))
+            assert st["n_touched"] == len(ot) and st["n_new"] == len(O.last_new())
+            assert keyset(G.vbh_scene_last_mc()) == keyset(O.last_mc_updated())
+    assert G.vbh_scene_status() == 0
+
+
+def corner_min_abs(O, keys, mism):
+    """min over the 8 corners of |F_oracle| for mismatched voxels (block i, local l)."""
+    out = []
+    for i, l in zip(*mism):
+        g = keys[i].astype(np.int64) * 8 + np.array([l % 8, (l // 8) % 8, l // 64])
+        cs = g[None] + OFFS
+        B = np.floor_divide(cs, 8)
+        F, W, _, found = O.read(B.astype(np.int32))
+        loc = cs - 8 * B
+        li = loc[:, 0] + 8 * loc[:, 1] + 64 * loc[:, 2]
+        out.append(np.abs(F[np.arange(8), li]).min())
+    return np.array(out)
+
+
+def compare_state(G, O):
+    gk = G.vbh_scene_export_blocks().cpu().numpy()
+    ok = O.blocks()
+    assert keyset(gk) == keyset(ok) and gk.shape[0] == ok.shape[0]
+    keys, _ = sort_keys(ok)
+    dk = to_dev(keys)
+    F, W, rgb, found = (t.cpu().numpy() for t in G.vbh_scene_read_blocks(dk))
+    oF, oW, orgb, ofound = O.read(keys)
+    assert found.all() and ofound.all()
+    assert np.array_equal(W, oW)
+    assert np.array_equal(rgb, orgb)
+    err = np.abs(F.astype(np.float64) - oF)
+    say(f"  blocks {keys.shape[0]}  max|F-F64| {err.max():.3g}  observed {(W > 0).sum()}")
+    assert err.max() <= F_TOL
+    # MC voxels, end to end: differences only where a corner's F is within 1e-5 of 0
+    gmc, grgb = (t.cpu().numpy() for t in G.vbh_stored_mc(dk))
+    omc, orgb2 = O.stored_mc(keys)
+    mism = np.nonzero(gmc != omc)
+    say(f"  MC end-to-end mismatches: {mism[0].size}")
+    if mism[0].size:
+        assert (corner_min_abs(O, keys, mism) <= F_TOL).all()
+    return keys, F, W, rgb, gmc, grgb
+
+
+def mc_on_identical_input(orc, vol, cam, keys, F, W, rgb, gmc, grgb):
+    O2 = orc.Scene(vol, cam)
+    assert O2.write(keys, F, W, rgb, 1) == 0
+    omc, orgb = O2.extract_mc(keys)
+    assert np.array_equal(gmc, omc)
+    assert np.array_equal(grgb, orgb)
+
+
+def test_tiny_full_pipeline(orc):
+    """32 noise-free 320x240 frames around the box room, 1 cm voxels, then MC of every block."""
+    vbh = require_gpu()
+    say("[scene tiny] generating")
+    _, depth, rgb, poses = configs.tiny_inputs(32)
+    G, O = make_pair(vbh, orc, configs.TINY_VOL, configs.TINY_CAM)
+    integrate_both(G, O, depth, rgb, poses, range(32))
+    keys, F, W, rgb_, gmc, grgb = compare_state(G, O)
+    mc_on_identical_input(orc, configs.TINY_VOL, configs.TINY_CAM, keys, F, W, rgb_, gmc, grgb)
+    # on-demand extraction equals the MC pool kept up to date frame by frame
+    emc, ergb = G.vbh_extract_mc_indices(to_dev(keys))
+    assert np.array_equal(emc.cpu().numpy(), gmc) and np.array_equal(ergb.cpu().numpy(), grgb)
+    assert (gmc > 0).sum() > 10000
+
+
+@pytest.mark.parametrize("hash_kind", [0, 1])
+def test_full_size_frames(orc, hash_kind):
+    """First frames of the 640x480 noisy sequence at 5 mm voxels in the full-size volume and
+    launch configuration (2^22 slots, 2^21-block pool)."""
+    vbh = require_gpu()
+    n = 6 if hash_kind == 0 else 3
+    say(f"[scene full] hash={hash_kind} generating {n} frames")
+    _, depth, rgb, poses = configs.full_inputs(range(n))
+    G, O = make_pair(vbh, orc, configs.FULL_VOL, configs.FULL_CAM, hash_kind)
+    integrate_both(G, O, depth, rgb, poses, range(n))
+    keys, F, W, rgb_, gmc, grgb = compare_state(G, O)
+    mc_on_identical_input(orc, configs.FULL_VOL, configs.FULL_CAM, keys, F, W, rgb_, gmc, grgb)
+
+
+def test_mc_identical_input_sphere_and_edges(orc):
+    vbh = require_gpu()
+    rng = np.random.default_rng(3)
+    keys = np.array([(x, y, z) for x in range(-1, 3) for y in range(-1, 2) for z in range(0, 3)], np.int32)
+    keys = keys[rng.permutation(keys.shape[0])[:30]]  # some neighbours missing
+    loc = np.arange(512)
+    l3 = np.stack([loc % 8, (loc // 8) % 8, loc // 64], -1)
+    g = keys[:, None, :].astype(np.int64) * 8 + l3[None]
+    F = (np.linalg.norm(g - np.array([4.3, 5.1, 9.7]), axis=-1) - 7.2).astype(np.float32) * 0.01
+    W = np.where(rng.random(F.shape) < 0.01, 0, rng.integers(1, 256, size=F.shape)).astype(np.uint8)
+    rgb = rng.integers(0, 256, size=F.shape + (3,)).astype(np.uint8)
+    G = vbh.Scene(vbh.make_params(configs.TINY_VOL, configs.TINY_CAM))
+    G.vbh_scene_write_blocks(to_dev(keys), to_dev(F), to_dev(W), to_dev(rgb), 1)
+    O = orc.Scene(configs.TINY_VOL, configs.TINY_CAM)
+    O.write(keys, F, W, rgb, 1)
+    q = np.concatenate([keys, np.array([[50, 50, 50]], np.int32)])  # plus a missing block
+    gmc, grgb = (t.cpu().numpy() for t in G.vbh_extract_mc_indices(to_dev(q)))
+    omc, orgb = O.extract_mc(q)
+    assert np.array_equal(gmc, omc) and np.array_equal(grgb, orgb)
+    assert (gmc[-1] == 0).all() and (gmc > 0).sum() > 100
+    smc, srgb = (t.cpu().numpy() for t in G.vbh_stored_mc(to_dev(q)))
+    assert np.array_equal(smc, omc) and np.array_equal(srgb, orgb)
+    # read-back of the written state
+    Fr, Wr, rgbr, found = (t.cpu().numpy() for t in G.vbh_scene_read_blocks(to_dev(q)))
+    assert np.array_equal(Fr[:-1], F) and np.array_equal(Wr[:-1], W) and np.array_equal(rgbr[:-1], rgb)
+    assert found[:-1].all() and found[-1] == 0
+
+
+def test_updated_since_against_oracle(orc):
+    vbh = require_gpu()
+    _, depth, rgb, poses = configs.tiny_inputs(8)
+    G, O = make_pair(vbh, orc, configs.TINY_VOL, configs.TINY_CAM)
+    marks = []
+    for f in range(8):
+        marks.append(O.log_length())
+        integrate_both(G, O, depth, rgb, poses, [f], first_id=f + 1, check_frames=False)
+    assert G.vbh_scene_stats()["log_length"] == O.log_length()
+    for cur in [0] + marks[1:] + [O.log_length(), O.log_length() + 5]:
+        keys, meta = G.vbh_updated_blocks_since(cur, 1 << 20)
+        n, nxt = (int(x) for x in meta.cpu())
+        ok, onxt = O.updated_since(cur, 1 << 20)
+        assert keyset(keys[:n]) == keyset(ok) and n == ok.shape[0]
+        assert nxt == onxt
+    # pages: union = everything, no duplicates, cursors advance
+    cur, seen = 0, []
+    while True:
+        keys, meta = G.vbh_updated_blocks_since(cur, 333)
+        n, nxt = (int(x) for x in meta.cpu())
+        seen += [tuple(k) for k in keys[:n].cpu().numpy()]
+        if n < 333:
+            assert nxt == O.log_length()
+            break
+        assert nxt > cur
+        cur = nxt
+    assert len(seen) == len(set(seen)) and set(seen) == keyset(O.blocks())
+    keys, meta = G.vbh_updated_blocks_since(7, 0)
+    assert [int(x) for x in meta.cpu()] == [0, 7]
+
+
+def test_scene_errors(orc):
+    vbh = require_gpu()
+    _, depth, rgb, poses = configs.tiny_inputs(2)
+    G = vbh.Scene(vbh.make_params(configs.TINY_VOL, configs.TINY_CAM))
+    G.vbh_integrate_frame(to_dev(depth[0].numpy()), None, poses[0], 5)
+    with pytest.raises(vbh.VbhError):
+        G.vbh_integrate_frame(to_dev(depth[1].numpy()), None, poses[1], 5)
+    small = configs.Volume(**{**configs.TINY_VOL.__dict__, "pool_blocks": 100})
+    G2 = vbh.Scene(vbh.make_params(small, configs.TINY_CAM))
+    G2.vbh_integrate_frame(to_dev(depth[0].numpy()), None, poses[0], 1)
+    assert G2.vbh_scene_status() == vbh.binding.VBH_EFULL_POOL
+    assert G2.vbh_scene_stats()["n_blocks"] == 100
+    G2.vbh_integrate_frame(to_dev(depth[1].numpy()), None, poses[1], 2)  # still runs, still reports
+    assert G2.vbh_scene_status() == vbh.binding.VBH_EFULL_POOL
+    tiny_log = configs.Volume(**{**configs.TINY_VOL.__dict__, "log_capacity": 10})
+    G3 = vbh.Scene(vbh.make_params(tiny_log, configs.TINY_CAM))
+    G3.vbh_integrate_frame(to_dev(depth[0].numpy()), None, poses[0], 1)
+    assert G3.vbh_scene_status() == vbh.binding.VBH_EFULL_LOG
