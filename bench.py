@@ -141,6 +141,8 @@ def main():
     ap.add_argument("--no-hash", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (scale reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported, this build runs "
@@ -154,6 +156,14 @@ def main():
     torch.cuda.set_device(0)
     vbh.lib()
     K, W = args.steps, args.warmup
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("[bench] copy calibration: 3 x 1 GiB device copies")
+        del src, dst
     depth, rgb, traj = stage_frames(max(K, W), "cuda")
     log("[bench] frames staged; fusing")
     dt, stage_ms, frames, stats, S = run_fusion(vbh, depth, rgb, traj, K, W)

@@ -29,14 +29,18 @@ constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 constexpr int kChunk = 2048;  // log entries per workgroup chunk in the paged walk
 constexpr int kRing = 8;      // per-frame counter ring
+constexpr int kMaxPartials = 1 << 16;
+// Same-address atomics serialise in L2 (about 10 ns each), so every kernel claims list
+// space and reports statistics once per workgroup, never once per wave.
 
 struct FrameCounters {
     unsigned int n_touched;
     unsigned int n_new;
-    unsigned int n_mc;
     unsigned int pad0;
+    unsigned int pad1;
     unsigned long long voxel_updates;
-    unsigned long long pad1;
+    unsigned long long log_base;  // log length when the update started; the update's MC
+                                  // list is its log segment [log_base, log_len)
 };
 
 struct Counters {
@@ -64,6 +68,7 @@ struct Dev {
     int32_t *mclist;     // [P] pool indices
     uint64_t *log;       // [L] (frame << 32) | pool
     int64_t *prefix;     // [max_chunks + 1] scratch of the paged walk
+    unsigned long long *partial;  // [kMaxPartials] per-workgroup statistics, reduced later
     int64_t pool_cap;
     uint64_t log_cap;
     Counters *C;
@@ -83,6 +88,47 @@ __device__ __forceinline__ bool depth_valid(float d, const Frame &f) {
     return d > 0.0f && d >= f.dmin && d <= f.dmax;
 }
 
+// Blocks in the MC update set of the update whose counters are fc (valid once its
+// marking has finished): the length of its log segment.
+__device__ __forceinline__ int64_t update_set_size(const Counters *C, const FrameCounters &fc) {
+    return int64_t(C->log_len - fc.log_base);
+}
+
+// Starts update `seq`: clears the counters two updates ahead in the ring and records
+// where this update's log segment begins.  Called by exactly one thread.
+__device__ __forceinline__ void begin_update(const Dev &S, int seq) {
+    FrameCounters z = {};
+    S.C->fc[(seq + 2) & (kRing - 1)] = z;
+    S.C->fc[seq & (kRing - 1)].log_base = S.C->log_len;
+}
+
+// Workgroup staging buffer for list appends: waves reserve space with one LDS atomic,
+// and the workgroup claims global space with one atomic per flush.
+template <int CAP>
+struct StageBuf {
+    int32_t item[CAP];
+    unsigned int count;
+    unsigned long long base;
+};
+
+template <int CAP>
+__device__ __forceinline__ void stage_reset(StageBuf<CAP> &b) {
+    if (threadIdx.x == 0) b.count = 0;
+    __syncthreads();
+}
+
+// Every lane of every wave may call; lanes with `put` store `v`.
+template <int CAP>
+__device__ __forceinline__ void stage_put(StageBuf<CAP> &b, bool put, int32_t v) {
+    const unsigned long long m = __ballot(put);
+    if (!m) return;
+    const int leader = __builtin_ctzll(m);
+    unsigned int pos = 0;
+    if (lane_id() == leader) pos = atomicAdd(&b.count, unsigned(__popcll(m)));
+    pos = __shfl(pos, leader);
+    if (put) b.item[pos + unsigned(lanes_below(m))] = v;
+}
+
 // ------------------------------------------------------------------ allocation
 // One wave per 8x8 pixel tile; lane = lx + 8 ly.  Each valid pixel takes 2m+1 band
 // samples at camera depth lam = (d - mu) + s*vs:
@@ -90,80 +136,195 @@ __device__ __forceinline__ bool depth_valid(float d, const Frame &f) {
 //   pw_i = ((R_i0 pc_x + R_i1 pc_y) + R_i2 pc_z) + t_i,  B_i = floor(pw_i / (8 vs)).
 // A sample whose key equals the lane's previous sample or the same sample of the left
 // or upper lane is skipped (that lane handles the key), which removes most duplicate
-// probes before they reach the table.  The first thread to raise a block's frame stamp
-// appends the slot to the touched list (wave-aggregated).
-__global__ void __launch_bounds__(kBlock) k_alloc(Dev S, Frame fr, const float *__restrict__ depth, uint32_t frame,
-                                                  int seq) {
+// probes before they reach the table.  Samples are processed in groups of kGroup: all
+// keys of a group are formed first, their home slots are read together, then their
+// frame stamps, so a lane keeps several independent loads in flight.  The first thread
+// to raise a block's frame stamp appends the slot to the touched list; appends are
+// gathered per lane and written with one atomic per wave.
+constexpr int kGroup = 5;
+constexpr int kAllocThreads = 512;  // 32x16 pixels: eight 8x8 tiles
+
+__global__ void __launch_bounds__(kAllocThreads) k_alloc(Dev S, Frame fr, const float *__restrict__ depth,
+                                                         uint32_t frame, int seq) {
+    constexpr int kCap = 2 * kAllocThreads * kGroup;
+    __shared__ StageBuf<kCap> tb;
+    __shared__ unsigned int n_claim, n_new_wg;
+    __shared__ unsigned long long pool_base;
     FrameCounters *fc = &S.C->fc[seq & (kRing - 1)];
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
-        FrameCounters z = {};
-        S.C->fc[(seq + 2) & (kRing - 1)] = z;
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) begin_update(S, seq);
+    if (threadIdx.x == 0) {
+        n_claim = 0;
+        n_new_wg = 0;
     }
+    stage_reset(tb);
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
     const int lx = lane & 7, ly = lane >> 3;
-    const int u = (blockIdx.x * 2 + (wave & 1)) * 8 + lx;
-    const int v = (blockIdx.y * 2 + (wave >> 1)) * 8 + ly;
+    const int u = (blockIdx.x * 4 + (wave & 3)) * 8 + lx;
+    const int v = (blockIdx.y * (kAllocThreads / 256) + (wave >> 2)) * 8 + ly;
     const bool inb = u < fr.W && v < fr.H;
     const float d = inb ? depth[int64_t(v) * fr.W + u] : 0.0f;
     const bool valid = inb && depth_valid(d, fr);
+    const bool wave_any = __ballot(valid) != 0;  // uniform per wave
     const float xn = (float(u) - fr.cx) / fr.fx;
     const float yn = (float(v) - fr.cy) / fr.fy;
     const float bs = 8.0f * fr.vs;
+    const int n_samples = 2 * fr.m_band + 1;
     uint64_t prev = kEmpty;
-    for (int s = 0; s <= 2 * fr.m_band; ++s) {
-        const float lam = (d - fr.mu) + float(s) * fr.vs;
-        bool ok = valid && lam > 0.0f;
-        uint64_t key = kEmpty;
-        int32_t B[3] = {0, 0, 0};
-        if (ok) {
-            const float pc[3] = {lam * xn, lam * yn, lam};
-            for (int i = 0; i < 3; ++i) {
-                const float pw = ((fr.P[i * 4 + 0] * pc[0] + fr.P[i * 4 + 1] * pc[1]) + fr.P[i * 4 + 2] * pc[2]) +
-                                 fr.P[i * 4 + 3];
-                const float q = floorf(pw / bs);
-                if (!(q >= -1048576.0f && q < 1048576.0f)) ok = false;
-                B[i] = ok ? int32_t(q) : 0;
-            }
-            if (ok)
-                key = pack_key(B[0], B[1], B[2]);
-            else
-                raise_err(&S.C->err, kErrKeyRange);
-        }
-        const uint64_t left = __shfl(key, (lane + 63) & 63);
-        const uint64_t up = __shfl(key, (lane + 56) & 63);
-        const bool dup = key == prev || (lx > 0 && key == left) || (ly > 0 && key == up);
-        const bool work = ok && !dup;
-        bool append = false, fresh = false;
-        int64_t slot = -1;
-        if (work) {
-            bool claimed;
-            slot = probe_claim(S.T, S.mask, key, home_slot(B[0], B[1], B[2], key, S.kind, S.mask), claimed);
-            if (slot < 0) {
-                raise_err(&S.C->err, kErrTableFull);
-            } else {
-                Slot *sl = S.T + slot;
-                if (claimed) {
-                    fresh = true;
-                    const unsigned long long pool = atomicAdd(&S.C->pool_next, 1ull);
-                    if (int64_t(pool) < S.pool_cap) {
-                        S.pool_key[pool] = key;
-                        st_val(sl, int32_t(pool));
-                    } else {
-                        st_val(sl, kNoPool);
-                        raise_err(&S.C->err, kErrPoolFull);
-                    }
+    for (int s0 = 0; s0 < n_samples; s0 += kGroup) {
+        uint64_t key[kGroup];
+        uint32_t work = 0;
+#pragma unroll
+        for (int i = 0; i < kGroup; ++i) {
+            const int s = s0 + i;
+            const float lam = (d - fr.mu) + float(s) * fr.vs;
+            bool ok = s < n_samples && valid && lam > 0.0f;
+            key[i] = kEmpty;
+            if (ok) {
+                const float pc[3] = {lam * xn, lam * yn, lam};
+                int32_t B[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const float pw = ((fr.P[c * 4 + 0] * pc[0] + fr.P[c * 4 + 1] * pc[1]) + fr.P[c * 4 + 2] * pc[2]) +
+                                     fr.P[c * 4 + 3];
+                    const float q = floorf(pw / bs);
+                    if (!(q >= -1048576.0f && q < 1048576.0f)) ok = false;
+                    B[c] = ok ? int32_t(q) : 0;
                 }
-                const uint32_t cur = __hip_atomic_load(&sl->stamp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (cur != frame) append = atomicMax(&sl->stamp, frame) < frame;
+                if (ok)
+                    key[i] = pack_key(B[0], B[1], B[2]);
+                else
+                    raise_err(&S.C->err, kErrKeyRange);
+            }
+            const uint64_t left = __shfl(key[i], (lane + 63) & 63);
+            const uint64_t up = __shfl(key[i], (lane + 56) & 63);
+            const bool dup = key[i] == prev || (lx > 0 && key[i] == left) || (ly > 0 && key[i] == up);
+            if (ok && !dup) work |= 1u << i;
+            prev = ok ? key[i] : kEmpty;
+        }
+        int32_t slot[kGroup];
+        uint32_t fresh = 0;
+        unsigned int claim_idx[kGroup];
+#pragma unroll
+        for (int i = 0; i < kGroup; ++i) {
+            slot[i] = -1;
+            claim_idx[i] = 0;
+        }
+        if (wave_any && __ballot(work != 0) != 0) {
+        // home slots, read together
+        uint32_t home[kGroup];
+        uint64_t first[kGroup];
+#pragma unroll
+        for (int i = 0; i < kGroup; ++i) {
+            first[i] = kEmpty;
+            home[i] = 0;
+            if (work & (1u << i)) {
+                int32_t x, y, z;
+                unpack_key(key[i], x, y, z);
+                home[i] = uint32_t(home_slot(x, y, z, key[i], S.kind, S.mask));
+                first[i] = ld_key(S.T + home[i]);
             }
         }
-        const unsigned int pos = wave_append<unsigned int>(append, &fc->n_touched);
-        if (append) S.touched[pos] = int32_t(slot);
-        const unsigned long long nm = __ballot(fresh);
-        if (nm && lane == __builtin_ctzll(nm)) atomicAdd(&fc->n_new, unsigned(__popcll(nm)));
-        prev = ok ? key : kEmpty;
+#pragma unroll
+        for (int i = 0; i < kGroup; ++i) {
+            slot[i] = -1;
+            claim_idx[i] = 0;
+            if (!(work & (1u << i))) continue;
+            if (first[i] == key[i]) {
+                slot[i] = int32_t(home[i]);
+                continue;
+            }
+            bool claimed;
+            slot[i] = int32_t(probe_claim(S.T, S.mask, key[i], home[i], claimed));
+            if (slot[i] < 0) raise_err(&S.C->err, kErrTableFull);
+            if (claimed) fresh |= 1u << i;
+        }
+        // claimed keys get workgroup-local indices; their pool blocks are handed out in
+        // one batch after the barrier below (readers do not need the value meanwhile)
+#pragma unroll
+        for (int i = 0; i < kGroup; ++i) {
+            const bool c = (fresh >> i) & 1u;
+            const unsigned long long m = __ballot(c);
+            if (m) {
+                const int leader = __builtin_ctzll(m);
+                unsigned int p0 = 0;
+                if (lane == leader) p0 = atomicAdd(&n_claim, unsigned(__popcll(m)));
+                p0 = __shfl(p0, leader);
+                claim_idx[i] = p0 + unsigned(lanes_below(m));
+            }
+        }
+        // frame stamps, read together; the winner of the stamp race appends
+        uint32_t stamp[kGroup];
+#pragma unroll
+        for (int i = 0; i < kGroup; ++i)
+            stamp[i] = slot[i] >= 0 ? __hip_atomic_load(&S.T[slot[i]].stamp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                    : frame;
+        uint32_t app = 0;
+#pragma unroll
+        for (int i = 0; i < kGroup; ++i)
+            if (stamp[i] != frame && atomicMax(&S.T[slot[i]].stamp, frame) < frame) app |= 1u << i;
+#pragma unroll
+        for (int i = 0; i < kGroup; ++i) stage_put(tb, (app >> i) & 1u, slot[i]);
+        }  // wave has work
+        __syncthreads();
+        if (n_claim) {  // uniform: one pool reservation per workgroup and group
+            if (threadIdx.x == 0) {
+                pool_base = atomicAdd(&S.C->pool_next, (unsigned long long)n_claim);
+                n_new_wg += n_claim;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < kGroup; ++i) {
+                if (!((fresh >> i) & 1u)) continue;
+                const unsigned long long pool = pool_base + claim_idx[i];
+                if (int64_t(pool) < S.pool_cap) {
+                    S.pool_key[pool] = key[i];
+                    st_val(S.T + slot[i], int32_t(pool));
+                } else {
+                    st_val(S.T + slot[i], kNoPool);
+                    raise_err(&S.C->err, kErrPoolFull);
+                }
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) n_claim = 0;
+            __syncthreads();
+        }
+        if (tb.count > unsigned(kCap - kAllocThreads * kGroup) || s0 + kGroup >= n_samples) {
+            // one combined 64-bit atomic claims touched-list space and counts new blocks
+            if (threadIdx.x == 0) {
+                const unsigned long long add = (unsigned long long)n_new_wg << 32 | tb.count;
+                const unsigned long long old =
+                    add ? atomicAdd(reinterpret_cast<unsigned long long *>(&fc->n_touched), add) : 0ull;
+                tb.base = old & 0xFFFFFFFFull;
+                n_new_wg = 0;
+            }
+            __syncthreads();
+            for (unsigned int i = threadIdx.x; i < tb.count; i += kAllocThreads) S.touched[tb.base + i] = tb.item[i];
+            __syncthreads();
+            if (threadIdx.x == 0) tb.count = 0;
+            __syncthreads();
+        }
     }
+}
+
+// ---------------------------------------------------------------- MC update set
+// Thread per (touched block, e in {0,1}^3): block B - e, if it exists, joins the frame's
+// MC update set (the touched blocks and their seven negative neighbours).  The first
+// thread to raise its MC stamp appends it to the MC list and to the update log.
+__device__ __forceinline__ bool try_mark(const Dev &S, int32_t target, uint32_t frame) {
+    if (target < 0) return false;
+    const uint32_t cur = __hip_atomic_load(&S.mc_stamp[target], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return cur != frame && atomicMax(&S.mc_stamp[target], frame) < frame;
+}
+
+// Appends a marked block at log position lpos (the MC list is the update's log segment).
+__device__ __forceinline__ void put_log(const Dev &S, const FrameCounters &fc, unsigned long long lpos, int32_t target,
+                                        uint32_t frame) {
+    S.mclist[lpos - fc.log_base] = target;
+    if (lpos < S.log_cap)
+        S.log[lpos] = (uint64_t(frame) << 32) | uint32_t(target);
+    else
+        raise_err(&S.C->err, kErrLogFull);
 }
 
 // ----------------------------------------------------------------- integration
@@ -173,6 +334,19 @@ __global__ void __launch_bounds__(kBlock) k_alloc(Dev S, Frame fr, const float *
 //   outside the image; skip unless the pixel depth d is valid; sdf = d - pc_z; skip if
 //   sdf < -mu.  Then F <- (W F + min(sdf, mu)) / (W + 1), W <- min(W + 1, 255) and each
 //   colour channel c <- (W c + c_obs + floor(n / 2)) / n with n = W + 1.
+// Exact floor(num / n) for num < 2^17 and 1 <= n <= 256 from a float reciprocal: the
+// float estimate is within one of the quotient, and one correction step fixes it.
+__device__ __forceinline__ uint32_t udiv_small(uint32_t num, uint32_t n, float inv_n) {
+    uint32_t q = uint32_t(float(num) * inv_n);
+    if (q * n > num) --q;
+    else if ((q + 1u) * n <= num) ++q;
+    return q;
+}
+
+// The eight voxels (lx, ly, 0..7) of a lane are projected first, then their depths are
+// loaded together, then the TSDF state (and observed colour) of the passing voxels is
+// loaded together; the slot of the wave's next block is fetched while the current one is
+// processed.  Each wave thus keeps up to 8 + 24 independent loads in flight.
 __global__ void __launch_bounds__(kBlock) k_integrate(Dev S, Frame fr, const float *__restrict__ depth,
                                                       const uint8_t *__restrict__ rgb, int seq) {
     const FrameCounters *fc = &S.C->fc[seq & (kRing - 1)];
@@ -182,91 +356,117 @@ __global__ void __launch_bounds__(kBlock) k_integrate(Dev S, Frame fr, const flo
     const int64_t gw = int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6);
     const int64_t nw = int64_t(gridDim.x) * kWaves;
     unsigned long long updates = 0;
+    Slot cur = {};
+    if (gw < n) cur = S.T[S.touched[gw]];
     for (int64_t t = gw; t < n; t += nw) {
-        const Slot *sl = S.T + S.touched[t];
-        const int32_t pool = sl->val;
-        if (pool < 0) continue;
+        const int32_t next_idx = t + nw < n ? S.touched[t + nw] : -1;
+        const int32_t pool = cur.val;
         int32_t bx, by, bz;
-        unpack_key(sl->key, bx, by, bz);
+        unpack_key(cur.key, bx, by, bz);
         const float dlx = float(8 * bx + lx) * fr.vs - fr.P[3];
         const float dly = float(8 * by + ly) * fr.vs - fr.P[7];
         const int64_t base = int64_t(pool) * 512 + lane;
-#pragma unroll 2
+        int32_t pix[8];
+        float pz[8];
+#pragma unroll
         for (int j = 0; j < 8; ++j) {
             const float dlz = float(8 * bz + j) * fr.vs - fr.P[11];
             const float pcx = (fr.P[0] * dlx + fr.P[4] * dly) + fr.P[8] * dlz;
             const float pcy = (fr.P[1] * dlx + fr.P[5] * dly) + fr.P[9] * dlz;
             const float pcz = (fr.P[2] * dlx + fr.P[6] * dly) + fr.P[10] * dlz;
-            if (!(pcz > 0.0f)) continue;
-            const float fu = floorf((fr.fx * (pcx / pcz) + fr.cx) + 0.5f);
-            const float fv = floorf((fr.fy * (pcy / pcz) + fr.cy) + 0.5f);
-            if (!(fu >= 0.0f && fu < float(fr.W) && fv >= 0.0f && fv < float(fr.H))) continue;
-            const int64_t pix = int64_t(fv) * fr.W + int64_t(fu);
-            const float d = depth[pix];
-            if (!depth_valid(d, fr)) continue;
-            const float sdf = d - pcz;
-            if (sdf < -fr.mu) continue;
-            const float tsdf = fminf(sdf, fr.mu);
-            const int64_t idx = base + 64 * j;
-            const float F = S.F[idx];
-            const uint32_t w = S.WRGB[idx];
-            const uint32_t w_old = w & 0xFFu;
+            pz[j] = pcz;
+            pix[j] = -1;
+            if (pool >= 0 && pcz > 0.0f) {
+                const float fu = floorf((fr.fx * (pcx / pcz) + fr.cx) + 0.5f);
+                const float fv = floorf((fr.fy * (pcy / pcz) + fr.cy) + 0.5f);
+                if (fu >= 0.0f && fu < float(fr.W) && fv >= 0.0f && fv < float(fr.H))
+                    pix[j] = int32_t(fv) * fr.W + int32_t(fu);
+            }
+        }
+        float d[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) d[j] = pix[j] >= 0 ? depth[pix[j]] : 0.0f;
+        const Slot nxt = next_idx >= 0 ? S.T[next_idx] : Slot{};
+        bool ok[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) ok[j] = pix[j] >= 0 && depth_valid(d[j], fr) && !(d[j] - pz[j] < -fr.mu);
+        float F[8];
+        uint32_t w[8];
+        uint32_t rg[8], bl[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            F[j] = 0.0f;
+            w[j] = 0u;
+            rg[j] = 0u;
+            bl[j] = 0u;
+            if (ok[j]) {
+                F[j] = S.F[base + 64 * j];
+                w[j] = S.WRGB[base + 64 * j];
+                if (rgb) {
+                    const uint8_t *o = rgb + int64_t(pix[j]) * 3;
+                    rg[j] = o[0];
+                    bl[j] = uint32_t(o[1]) | uint32_t(o[2]) << 8;
+                }
+            }
+        }
+        float Fn[8];
+        uint32_t Wn[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {  // branch-free: computed for every voxel, stored if ok
+            const float tsdf = fminf(d[j] - pz[j], fr.mu);
+            const uint32_t w_old = w[j] & 0xFFu;
             const uint32_t nn = w_old + 1u;
-            S.F[idx] = (float(w_old) * F + tsdf) / float(nn);
+            Fn[j] = (float(w_old) * F[j] + tsdf) / float(nn);
             uint32_t out = nn > 255u ? 255u : nn;
             if (rgb) {
-                const uint8_t *o = rgb + pix * 3;
+                const float inv = 1.0f / float(nn);
+                const uint32_t o3 = rg[j] | bl[j] << 8;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    const uint32_t cur = (w >> (8 * (c + 1))) & 0xFFu;
-                    out |= ((w_old * cur + uint32_t(o[c]) + (nn >> 1)) / nn) << (8 * (c + 1));
+                    const uint32_t cur_c = (w[j] >> (8 * (c + 1))) & 0xFFu;
+                    const uint32_t num = w_old * cur_c + ((o3 >> (8 * c)) & 0xFFu) + (nn >> 1);
+                    out |= udiv_small(num, nn, inv) << (8 * (c + 1));
                 }
             } else {
-                out |= w & 0xFFFFFF00u;
+                out |= w[j] & 0xFFFFFF00u;
             }
-            S.WRGB[idx] = out;
-            ++updates;
+            Wn[j] = out;
         }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (ok[j]) {
+                S.F[base + 64 * j] = Fn[j];
+                S.WRGB[base + 64 * j] = Wn[j];
+                ++updates;
+            }
+        }
+        cur = nxt;
     }
+    __shared__ unsigned long long wg_updates;
+    if (threadIdx.x == 0) wg_updates = 0;
+    __syncthreads();
     updates = wave_sum(updates);
-    if (lane == 0 && updates) atomicAdd((unsigned long long *)&S.C->fc[seq & (kRing - 1)].voxel_updates, updates);
+    if (lane == 0 && updates) atomicAdd(&wg_updates, updates);  // LDS atomic
+    __syncthreads();
+    if (threadIdx.x == 0) S.partial[blockIdx.x] = wg_updates;
 }
 
-// ---------------------------------------------------------------- MC update set
-// Thread per (touched block, e in {0,1}^3): block B - e, if it exists, joins the frame's
-// MC update set (the touched blocks and their seven negative neighbours).  The first
-// thread to raise its MC stamp appends it to the MC list and to the update log.
-__device__ __forceinline__ void mark_one(const Dev &S, int32_t target, uint32_t frame, FrameCounters *fc, bool active) {
-    bool mark = false;
-    if (active && target >= 0) {
-        const uint32_t cur = __hip_atomic_load(&S.mc_stamp[target], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (cur != frame) mark = atomicMax(&S.mc_stamp[target], frame) < frame;
-    }
-    const unsigned int pos = wave_append<unsigned int>(mark, &fc->n_mc);
-    const unsigned long long lpos = wave_append<unsigned long long>(mark, &S.C->log_len);
-    if (mark) {
-        S.mclist[pos] = target;
-        if (lpos < S.log_cap)
-            S.log[lpos] = (uint64_t(frame) << 32) | uint32_t(target);
-        else
-            raise_err(&S.C->err, kErrLogFull);
-    }
-}
-
-__global__ void __launch_bounds__(kBlock) k_mc_mark(Dev S, uint32_t frame, int seq) {
+// Thread per (touched block, e in {0,1}^3): block B - e, if it exists, joins the
+// update's MC set (the touched blocks and their seven negative neighbours).  The first
+// thread to raise its MC stamp appends it; appends are staged per workgroup in LDS and
+// claimed in the log with one atomic per workgroup.
+constexpr int kMarkThreads = 1024;
+__global__ void __launch_bounds__(kMarkThreads) k_mc_mark(Dev S, uint32_t frame, int seq) {
+    constexpr int kCap = 4 * kMarkThreads;
+    __shared__ StageBuf<kCap> mb;
     FrameCounters *fc = &S.C->fc[seq & (kRing - 1)];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        S.C->tot_touched += fc->n_touched;
-        S.C->tot_voxel_updates += fc->voxel_updates;
-    }
     const int64_t total = int64_t(fc->n_touched) * 8;
-    const int lane = lane_id();
-    const int64_t stride = int64_t(gridDim.x) * kBlock;
-    for (int64_t b = int64_t(blockIdx.x) * kBlock + (threadIdx.x & ~63); b < total; b += stride) {
-        const int64_t i = b + lane;
-        const bool active = i < total;
+    const int64_t stride = int64_t(gridDim.x) * kMarkThreads;
+    stage_reset(mb);
+    for (int64_t b0 = int64_t(blockIdx.x) * kMarkThreads; b0 < total; b0 += stride) {  // uniform per workgroup
+        const int64_t i = b0 + threadIdx.x;
         int32_t target = -1;
-        if (active) {
+        if (i < total) {
             const Slot *sl = S.T + S.touched[i >> 3];
             const int32_t pool = sl->val;
             const int e = int(i & 7);
@@ -285,7 +485,17 @@ __global__ void __launch_bounds__(kBlock) k_mc_mark(Dev S, uint32_t frame, int s
                 }
             }
         }
-        mark_one(S, target, frame, fc, active);
+        stage_put(mb, try_mark(S, target, frame), target);
+        __syncthreads();
+        if (mb.count > unsigned(kCap - kMarkThreads) || b0 + stride >= total) {
+            if (threadIdx.x == 0) mb.base = mb.count ? atomicAdd(&S.C->log_len, (unsigned long long)mb.count) : 0;
+            __syncthreads();
+            for (unsigned int k = threadIdx.x; k < mb.count; k += kMarkThreads)
+                put_log(S, *fc, mb.base + k, mb.item[k], frame);
+            __syncthreads();
+            if (threadIdx.x == 0) mb.count = 0;
+            __syncthreads();
+        }
     }
 }
 
@@ -302,16 +512,23 @@ __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ float halo_value(const Dev &S, int32_t pool, int l) {
-    if (pool < 0) return __builtin_nanf("");
-    const int64_t idx = int64_t(pool) * 512 + l;
-    const uint32_t w = S.WRGB[idx];
-    return (w & 0xFFu) ? S.F[idx] : __builtin_nanf("");
-}
+// Value staged in the halo: F if the voxel was observed (W > 0), else NaN.
+__device__ __forceinline__ float staged(float f, uint32_t w) { return (w & 0xFFu) ? f : __builtin_nanf(""); }
 
 // Computes the 512 MC voxels of block `pool` (key B) into out[j] for voxel lane + 64 j.
+// Loads are issued in two batches (own block + neighbour probes, then the 217 halo
+// voxels from always-valid addresses) so each wave waits on memory twice per block.
 __device__ __forceinline__ void mc_block(const Dev &S, int32_t pool, uint64_t key, float *halo, uint32_t (&out)[8]) {
     const int lane = lane_id();
+    const int lx = lane & 7, ly = lane >> 3;
+    uint32_t own[8];
+    float fo[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int64_t idx = int64_t(pool) * 512 + lane + 64 * j;
+        own[j] = S.WRGB[idx];
+        fo[j] = S.F[idx];
+    }
     int32_t bx, by, bz;
     unpack_key(key, bx, by, bz);
     int32_t nb = -1;
@@ -330,34 +547,39 @@ __device__ __forceinline__ void mc_block(const Dev &S, int32_t pool, uint64_t ke
     int32_t nbs[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) nbs[e] = __shfl(nb, e);
-    uint32_t own[8];
-    const int lx = lane & 7, ly = lane >> 3;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const int64_t idx = int64_t(pool) * 512 + lane + 64 * j;
-        const uint32_t w = S.WRGB[idx];
-        own[j] = w;
-        halo[lx + 9 * ly + 81 * j] = (w & 0xFFu) ? S.F[idx] : __builtin_nanf("");
-    }
-    // faces: x = 8 from block +x (local x = 0), y = 8 from +y, z = 8 from +z
-    {
-        const int a = lane & 7, b = lane >> 3;
-        halo[8 + 9 * a + 81 * b] = halo_value(S, nbs[1], 0 + 8 * a + 64 * b);
-        halo[a + 9 * 8 + 81 * b] = halo_value(S, nbs[2], a + 0 + 64 * b);
-        halo[a + 9 * b + 81 * 8] = halo_value(S, nbs[4], a + 8 * b + 0);
-    }
-    // edges and the corner
+    // halo items of this lane: faces x = 8 (from +x, local x = 0), y = 8, z = 8, and for
+    // lanes < 25 one edge/corner voxel; a missing neighbour reads the own block instead
+    // (always valid memory) and is masked to NaN afterwards
+    const int a = lane & 7, b = lane >> 3;
+    int32_t src_blk[4];
+    int src_loc[4], dst[4];
+    src_blk[0] = nbs[1]; src_loc[0] = 8 * a + 64 * b; dst[0] = 8 + 9 * a + 81 * b;
+    src_blk[1] = nbs[2]; src_loc[1] = a + 64 * b;     dst[1] = a + 9 * 8 + 81 * b;
+    src_blk[2] = nbs[4]; src_loc[2] = a + 8 * b;      dst[2] = a + 9 * b + 81 * 8;
     if (lane < 8) {
-        halo[8 + 9 * 8 + 81 * lane] = halo_value(S, nbs[3], 0 + 0 + 64 * lane);      // +x+y
+        src_blk[3] = nbs[3]; src_loc[3] = 64 * lane;   dst[3] = 8 + 9 * 8 + 81 * lane;  // +x+y edge
     } else if (lane < 16) {
-        const int a = lane - 8;
-        halo[8 + 9 * a + 81 * 8] = halo_value(S, nbs[5], 0 + 8 * a + 0);            // +x+z
+        src_blk[3] = nbs[5]; src_loc[3] = 8 * (lane - 8); dst[3] = 8 + 9 * (lane - 8) + 81 * 8;  // +x+z
     } else if (lane < 24) {
-        const int a = lane - 16;
-        halo[a + 9 * 8 + 81 * 8] = halo_value(S, nbs[6], a + 0 + 0);                // +y+z
+        src_blk[3] = nbs[6]; src_loc[3] = lane - 16;   dst[3] = (lane - 16) + 9 * 8 + 81 * 8;  // +y+z
     } else if (lane == 24) {
-        halo[8 + 9 * 8 + 81 * 8] = halo_value(S, nbs[7], 0);                        // +x+y+z
+        src_blk[3] = nbs[7]; src_loc[3] = 0;           dst[3] = 8 + 9 * 8 + 81 * 8;         // +x+y+z
+    } else {
+        src_blk[3] = -1; src_loc[3] = 0; dst[3] = -1;
     }
+    float hf[4];
+    uint32_t hw[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int64_t idx = int64_t(src_blk[i] >= 0 ? src_blk[i] : pool) * 512 + src_loc[i];
+        hf[i] = S.F[idx];
+        hw[i] = S.WRGB[idx];
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) halo[lx + 9 * ly + 81 * j] = staged(fo[j], own[j]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        if (dst[i] >= 0) halo[dst[i]] = src_blk[i] >= 0 ? staged(hf[i], hw[i]) : __builtin_nanf("");
     wave_sync_lds();
     constexpr int off[8] = {0, 1, 10, 9, 81, 82, 91, 90};
 #pragma unroll
@@ -380,11 +602,29 @@ __device__ __forceinline__ void mc_block(const Dev &S, int32_t pool, uint64_t ke
 }
 
 // Per-frame form: MC list -> MC pool.
-__global__ void __launch_bounds__(kBlock) k_mc_extract(Dev S, int seq) {
+// Workgroup 0 also folds the integration kernel's n_partials per-workgroup voxel counts
+// into the update's statistics.
+__global__ void __launch_bounds__(kBlock) k_mc_extract(Dev S, int seq, int n_partials) {
     __shared__ float halo_all[kWaves][kHalo];
+    __shared__ unsigned long long red[kWaves];
     float *halo = halo_all[threadIdx.x >> 6];
-    const int64_t n = S.C->fc[seq & (kRing - 1)].n_mc;
-    if (blockIdx.x == 0 && threadIdx.x == 0) S.C->tot_mc += n;
+    FrameCounters &fcr = S.C->fc[seq & (kRing - 1)];
+    const int64_t n = update_set_size(S.C, fcr);
+    if (blockIdx.x == 0) {
+        unsigned long long v = 0;
+        for (int i = threadIdx.x; i < n_partials; i += kBlock) v += S.partial[i];
+        v = wave_sum(v);
+        if (lane_id() == 0) red[threadIdx.x >> 6] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long tot = 0;
+            for (int w = 0; w < kWaves; ++w) tot += red[w];
+            fcr.voxel_updates = tot;
+            S.C->tot_mc += n;
+            S.C->tot_touched += fcr.n_touched;
+            S.C->tot_voxel_updates += tot;
+        }
+    }
     const int lane = lane_id();
     const int64_t gw = int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6);
     const int64_t nw = int64_t(gridDim.x) * kWaves;
@@ -462,10 +702,7 @@ __global__ void __launch_bounds__(kBlock) k_read_blocks(Dev S, const int32_t *ke
 // Thread per key: insert (allocating a pool block), stamp as touched by `frame`.
 __global__ void __launch_bounds__(kBlock) k_load_claim(Dev S, const int32_t *keys, int64_t n, uint32_t frame, int seq) {
     FrameCounters *fc = &S.C->fc[seq & (kRing - 1)];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        FrameCounters z = {};
-        S.C->fc[(seq + 2) & (kRing - 1)] = z;
-    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) begin_update(S, seq);
     const int64_t stride = int64_t(gridDim.x) * kBlock;
     for (int64_t b = int64_t(blockIdx.x) * kBlock + (threadIdx.x & ~63); b < n; b += stride) {
         const int64_t i = b + lane_id();
@@ -532,7 +769,7 @@ __global__ void __launch_bounds__(kBlock) k_keys_of(Dev S, int which, int seq, i
         n = int64_t(pn) < S.pool_cap ? int64_t(pn) : S.pool_cap;
     } else {
         const FrameCounters &fc = S.C->fc[seq & (kRing - 1)];
-        n = which == 1 ? fc.n_touched : fc.n_mc;
+        n = which == 1 ? int64_t(fc.n_touched) : update_set_size(S.C, fc);
     }
     if (n > cap) n = cap;
     for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock) {
@@ -662,7 +899,7 @@ __global__ void k_read_counters(const Counters *C, int seq, unsigned long long *
     out[9] = C->tot_voxel_updates;
     out[0] = fc.n_touched;
     out[1] = fc.n_new;
-    out[2] = fc.n_mc;
+    out[2] = C->log_len - fc.log_base;
     out[3] = fc.voxel_updates;
     out[4] = C->pool_next;
     out[5] = C->log_len;
@@ -684,7 +921,7 @@ struct vbh_scene {
     int seq = 0;        // number of updates so far (ring index of the next one)
     int cus = 256;      // compute units of the device the scene lives on
     uint32_t last_frame = 0;
-    void *mem[12] = {};
+    void *mem[13] = {};
     bool timing = false;
     std::vector<std::array<hipEvent_t, 5>> ev_pending, ev_free;
 };
@@ -718,8 +955,8 @@ unsigned wave_grid(const vbh_scene *s, int64_t cap_items) {
 // Runs the MC update for the blocks in the touched list of update `seq`.
 int mc_update(vbh_scene *s, uint32_t frame, int seq, hipStream_t st) {
     const unsigned g = unsigned(s->cus) * 8;
-    k_mc_mark<<<g, kBlock, 0, st>>>(s->d, frame, seq);
-    k_mc_extract<<<g, kBlock, 0, st>>>(s->d, seq);
+    k_mc_mark<<<unsigned(s->cus) * 2, kMarkThreads, 0, st>>>(s->d, frame, seq);
+    k_mc_extract<<<g, kBlock, 0, st>>>(s->d, seq, 0);
     VBH_LAUNCHED();
     return VBH_OK;
 }
@@ -772,8 +1009,9 @@ int vbh_scene_create(const vbh_params *p, vbh_scene **out) {
     s->max_chunks = (p->log_capacity + kChunk - 1) / kChunk + 1;
     const size_t sizes[] = {p->slots * sizeof(Slot), P * 512 * sizeof(float), P * 512 * 4, P * 512 * 4,
                             P * 8,                  P * 4,                     p->slots * 4, P * 4,
-                            size_t(p->log_capacity) * 8, size_t(s->max_chunks) * 8, sizeof(Counters), 64 * 8};
-    for (int i = 0; i < 12; ++i) {
+                            size_t(p->log_capacity) * 8, size_t(s->max_chunks) * 8, sizeof(Counters), 64 * 8,
+                            size_t(kMaxPartials) * 8};
+    for (int i = 0; i < 13; ++i) {
         if (hipMalloc(&s->mem[i], sizes[i]) != hipSuccess) {
             vbh_scene_destroy(s);
             return VBH_ENOMEM;
@@ -797,6 +1035,7 @@ int vbh_scene_create(const vbh_params *p, vbh_scene **out) {
     s->C = static_cast<Counters *>(s->mem[10]);
     d.C = s->C;
     s->hostbuf = static_cast<unsigned long long *>(s->mem[11]);
+    d.partial = static_cast<unsigned long long *>(s->mem[12]);
     bool ok = vbh::table_init(d.T, p->slots, nullptr) == VBH_OK;
     for (int i = 1; i <= 5 && ok; ++i) ok = hipMemset(s->mem[i], 0, sizes[i]) == hipSuccess;
     ok = ok && hipMemset(s->C, 0, sizeof(Counters)) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
@@ -837,16 +1076,18 @@ int vbh_integrate_frame(vbh_scene *s, const float *d_depth, const uint8_t *d_rgb
         s->ev_pending.push_back(ev);
     }
     auto mark = [&](int i) { return s->timing ? hipEventRecord(ev[i], st) : hipSuccess; };
-    dim3 ga(unsigned((s->p.width + 15) / 16), unsigned((s->p.height + 15) / 16));
+    dim3 ga(unsigned((s->p.width + 31) / 32), unsigned((s->p.height + 8 * (kAllocThreads / 256) - 1) /
+                                                        (8 * (kAllocThreads / 256))));
     const unsigned g = unsigned(s->cus) * 8;
+    const unsigned gi = unsigned(s->cus) * 8;
     VBH_HIP(mark(0));
-    k_alloc<<<ga, kBlock, 0, st>>>(s->d, fr, d_depth, frame_id, seq);
+    k_alloc<<<ga, kAllocThreads, 0, st>>>(s->d, fr, d_depth, frame_id, seq);
     VBH_HIP(mark(1));
-    k_integrate<<<g, kBlock, 0, st>>>(s->d, fr, d_depth, d_rgb, seq);
+    k_integrate<<<gi, kBlock, 0, st>>>(s->d, fr, d_depth, d_rgb, seq);
     VBH_HIP(mark(2));
-    k_mc_mark<<<g, kBlock, 0, st>>>(s->d, frame_id, seq);
+    k_mc_mark<<<unsigned(s->cus) * 2, kMarkThreads, 0, st>>>(s->d, frame_id, seq);
     VBH_HIP(mark(3));
-    k_mc_extract<<<g, kBlock, 0, st>>>(s->d, seq);
+    k_mc_extract<<<g / 2, kBlock, 0, st>>>(s->d, seq, int(gi));
     VBH_HIP(mark(4));
     VBH_LAUNCHED();
     s->seq = seq + 1;
