@@ -220,3 +220,78 @@ class Scene:
 
     def error(self):
         return int(lib().orc_scene_error(self.h))
+
+
+class DiffProblemStruct(C.Structure):
+    _fields_ = [("p", OrcParams), ("n_frames", C.c_int32), ("depth", C.c_void_p), ("poses", C.c_void_p),
+                ("n_samples", C.c_int64), ("sample_frame", C.c_void_p), ("sample_pixel", C.c_void_p)]
+
+
+class Diff:
+    """Frozen-branch float64 forward and gradient of L = sum_k F_tri(x_k)^2 (see diff.cpp)."""
+
+    def __init__(self, vol, cam, depth, poses, sample_frame, sample_pixel):
+        self.depth = np.ascontiguousarray(depth, np.float32)
+        self.poses = np.ascontiguousarray(np.asarray(poses, np.float64).reshape(-1, 3, 4), np.float32)
+        self.sf = np.ascontiguousarray(sample_frame, np.int32)
+        self.sp = np.ascontiguousarray(sample_pixel, np.int32)
+        self.F, self.HW = self.depth.shape[0], cam.width * cam.height
+        prob = DiffProblemStruct(make_params(vol, cam), self.F, self.depth.ctypes.data, self.poses.ctypes.data,
+                                 self.sf.size, self.sf.ctypes.data, self.sp.ctypes.data)
+        self.h = lib().orc_diff_new(C.byref(prob))
+        if not self.h:
+            raise ValueError("invalid differentiable problem")
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().orc_diff_free(self.h)
+            self.h = None
+
+    def loss(self, d_depth=None, scale=0.0, xi=None):
+        dd = None if d_depth is None else np.ascontiguousarray(d_depth, np.float64)
+        x = None if xi is None else np.ascontiguousarray(xi, np.float64)
+        return float(lib().orc_diff_loss(self.h, _p(dd), scale, _p(x)))
+
+    def grad(self):
+        gD = np.empty(self.F * self.HW, np.float64)
+        gx = np.empty(self.F * 6, np.float64)
+        lib().orc_diff_grad(self.h, _p(gD), _p(gx))
+        return gD.reshape(self.F, -1), gx.reshape(self.F, 6)
+
+    def info(self):
+        kept, ngv = C.c_int64(), C.c_int64()
+        f = np.empty(self.sf.size, np.float64)
+        nb = lib().orc_diff_info(self.h, C.byref(kept), C.byref(ngv), _p(f))
+        return {"blocks": int(nb), "kept": kept.value, "grad_voxels": ngv.value, "f_samples": f}
+
+    # Central differences with step h.  points=3: (L(h) - L(-h)) / 2h; points=5 adds one
+    # Richardson step, (8 (L(h) - L(-h)) - (L(2h) - L(-2h))) / 12h, removing the O(h^2) term.
+    @staticmethod
+    def _central(fn, h, points):
+        d1 = (fn(h) - fn(-h)) / (2 * h)
+        if points == 3:
+            return d1
+        d2 = (fn(2 * h) - fn(-2 * h)) / (4 * h)
+        return (4 * d1 - d2) / 3
+
+    def fd_pose(self, f, a, h=1e-4, points=5):
+        def fn(t):
+            xi = np.zeros((self.F, 6))
+            xi[f, a] = t
+            return self.loss(xi=xi)
+        return self._central(fn, h, points)
+
+    def fd_depth(self, f, pix, h=1e-4, points=5):
+        v = np.zeros((self.F, self.HW))
+        v[f, pix] = 1.0
+        return self._central(lambda t: self.loss(v, t), h, points)
+
+    def fd_direction(self, v_depth, v_xi, h=1e-4, points=5):
+        return self._central(lambda t: self.loss(v_depth, t, t * v_xi), h, points)
+
+
+def rel_err(g, g_ref, scale_ref=None):
+    """|g - g_ref| / max(|g_ref|, 1e-3 max|g_ref|) elementwise."""
+    g, g_ref = np.asarray(g, np.float64), np.asarray(g_ref, np.float64)
+    s = np.abs(g_ref).max() if scale_ref is None else scale_ref
+    return np.abs(g - g_ref) / np.maximum(np.abs(g_ref), 1e-3 * s)

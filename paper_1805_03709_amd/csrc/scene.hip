@@ -13,76 +13,11 @@
 #include <new>
 #include <vector>
 
-#include "device.hpp"
-#include "host.hpp"
-#include "vbh.h"
+#include "scene.hpp"
 
 using namespace vbh;
 
-namespace vbh {
-int table_init(Slot *T, uint64_t n, hipStream_t st);
-}
-
 namespace {
-
-constexpr int kBlock = 256;
-constexpr int kWaves = kBlock / 64;
-constexpr int kChunk = 2048;  // log entries per workgroup chunk in the paged walk
-constexpr int kRing = 8;      // per-frame counter ring
-constexpr int kMaxPartials = 1 << 16;
-// Same-address atomics serialise in L2 (about 10 ns each), so every kernel claims list
-// space and reports statistics once per workgroup, never once per wave.
-
-struct FrameCounters {
-    unsigned int n_touched;
-    unsigned int n_new;
-    unsigned int pad0;
-    unsigned int pad1;
-    unsigned long long voxel_updates;
-    unsigned long long log_base;  // log length when the update started; the update's MC
-                                  // list is its log segment [log_base, log_len)
-};
-
-struct Counters {
-    FrameCounters fc[kRing];
-    unsigned long long pool_next;  // pool blocks handed out (may exceed capacity)
-    unsigned long long log_len;    // log entries written or attempted
-    unsigned long long tot_touched;  // sums over all updates so far
-    unsigned long long tot_mc;
-    unsigned long long tot_voxel_updates;
-    uint32_t err;
-    uint32_t pad[7];
-};
-
-// Device view of a scene, passed by value to kernels.
-struct Dev {
-    Slot *T;
-    uint64_t mask;
-    int kind;
-    float *F;            // [P][512]
-    uint32_t *WRGB;      // [P][512] W | R<<8 | G<<16 | B<<24
-    uint32_t *MCV;       // [P][512] index | R<<8 | G<<16 | B<<24
-    uint64_t *pool_key;  // [P]
-    uint32_t *mc_stamp;  // [P]
-    int32_t *touched;    // [slots] slot indices
-    int32_t *mclist;     // [P] pool indices
-    uint64_t *log;       // [L] (frame << 32) | pool
-    int64_t *prefix;     // [max_chunks + 1] scratch of the paged walk
-    unsigned long long *partial;  // [kMaxPartials] per-workgroup statistics, reduced later
-    int64_t pool_cap;
-    uint64_t log_cap;
-    Counters *C;
-};
-
-// Camera, pose and volume constants of one frame.
-struct Frame {
-    float P[12];  // camera-to-world, row-major [R|t]
-    float fx, fy, cx, cy;
-    int W, H;
-    float dmin, dmax;
-    float vs, mu;
-    int m_band;
-};
 
 __device__ __forceinline__ bool depth_valid(float d, const Frame &f) {
     return d > 0.0f && d >= f.dmin && d <= f.dmax;
@@ -908,42 +843,29 @@ __global__ void k_read_counters(const Counters *C, int seq, unsigned long long *
 
 __global__ void k_clear_err(Counters *C) { C->err = 0; }
 
+// Zeroes the voxel, MC and stamp state of every handed-out pool block, then the counters.
+__global__ void __launch_bounds__(kBlock) k_reset_blocks(Dev S) {
+    const unsigned long long pn = S.C->pool_next;
+    const int64_t n = int64_t(pn) < S.pool_cap ? int64_t(pn) : S.pool_cap;
+    for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n * 512; i += int64_t(gridDim.x) * kBlock) {
+        S.F[i] = 0.0f;
+        S.WRGB[i] = 0u;
+        S.MCV[i] = 0u;
+        if ((i & 511) == 0) {
+            S.pool_key[i >> 9] = 0;
+            S.mc_stamp[i >> 9] = 0;
+        }
+    }
+}
+
+__global__ void k_zero_counters(Counters *C) {
+    uint32_t *w = reinterpret_cast<uint32_t *>(C);
+    for (unsigned i = threadIdx.x; i < sizeof(Counters) / 4; i += blockDim.x) w[i] = 0;
+}
+
 }  // namespace
 
-// ======================================================================= host side
-struct vbh_scene {
-    vbh_params p{};
-    int m_band = 0;
-    Dev d{};
-    Counters *C = nullptr;
-    unsigned long long *hostbuf = nullptr;  // device staging for counters
-    int64_t max_chunks = 0;
-    int seq = 0;        // number of updates so far (ring index of the next one)
-    int cus = 256;      // compute units of the device the scene lives on
-    uint32_t last_frame = 0;
-    void *mem[13] = {};
-    bool timing = false;
-    std::vector<std::array<hipEvent_t, 5>> ev_pending, ev_free;
-};
-
 namespace {
-
-Frame make_frame(const vbh_scene *s, const float *pose) {
-    Frame f;
-    std::memcpy(f.P, pose, sizeof(f.P));
-    f.fx = s->p.fx;
-    f.fy = s->p.fy;
-    f.cx = s->p.cx;
-    f.cy = s->p.cy;
-    f.W = s->p.width;
-    f.H = s->p.height;
-    f.dmin = s->p.depth_min;
-    f.dmax = s->p.depth_max;
-    f.vs = s->p.voxel_size;
-    f.mu = s->p.trunc;
-    f.m_band = s->m_band;
-    return f;
-}
 
 unsigned wave_grid(const vbh_scene *s, int64_t cap_items) {
     // waves-per-item kernels: enough workgroups to fill every CU several times over
@@ -989,6 +911,71 @@ int keys_of(vbh_scene *s, int which, int32_t *d_keys, int64_t cap, int64_t *h_co
 }
 
 }  // namespace
+
+namespace vbh {
+Frame make_frame(const vbh_scene *s, const float *pose) {
+    Frame f;
+    std::memcpy(f.P, pose, sizeof(f.P));
+    f.fx = s->p.fx;
+    f.fy = s->p.fy;
+    f.cx = s->p.cx;
+    f.cy = s->p.cy;
+    f.W = s->p.width;
+    f.H = s->p.height;
+    f.dmin = s->p.depth_min;
+    f.dmax = s->p.depth_max;
+    f.vs = s->p.voxel_size;
+    f.mu = s->p.trunc;
+    f.m_band = s->m_band;
+    return f;
+}
+}  // namespace vbh
+
+namespace vbh {
+int scene_fuse(vbh_scene *s, const float *d_depth, const uint8_t *d_rgb, const float *pose, uint32_t frame,
+               bool with_mc, hipStream_t st) {
+    const Frame fr = make_frame(s, pose);
+    const int seq = s->seq;
+    std::array<hipEvent_t, 5> ev{};
+    if (s->timing) {
+        if (s->ev_free.empty()) {
+            for (auto &e : ev) VBH_HIP(hipEventCreate(&e));
+        } else {
+            ev = s->ev_free.back();
+            s->ev_free.pop_back();
+        }
+        s->ev_pending.push_back(ev);
+    }
+    auto mark = [&](int i) { return s->timing ? hipEventRecord(ev[i], st) : hipSuccess; };
+    dim3 ga(unsigned((s->p.width + 31) / 32), unsigned((s->p.height + 8 * (kAllocThreads / 256) - 1) /
+                                                        (8 * (kAllocThreads / 256))));
+    const unsigned g = unsigned(s->cus) * 8;
+    const unsigned gi = unsigned(s->cus) * 8;
+    VBH_HIP(mark(0));
+    k_alloc<<<ga, kAllocThreads, 0, st>>>(s->d, fr, d_depth, frame, seq);
+    VBH_HIP(mark(1));
+    k_integrate<<<gi, kBlock, 0, st>>>(s->d, fr, d_depth, d_rgb, seq);
+    VBH_HIP(mark(2));
+    if (with_mc) k_mc_mark<<<unsigned(s->cus) * 2, kMarkThreads, 0, st>>>(s->d, frame, seq);
+    VBH_HIP(mark(3));
+    if (with_mc) k_mc_extract<<<g / 2, kBlock, 0, st>>>(s->d, seq, int(gi));
+    VBH_HIP(mark(4));
+    VBH_LAUNCHED();
+    s->seq = seq + 1;
+    s->last_frame = frame;
+    return VBH_OK;
+}
+
+int scene_reset(vbh_scene *s, hipStream_t st) {
+    if (int rc = table_init(s->d.T, s->p.slots, st)) return rc;
+    k_reset_blocks<<<unsigned(s->cus) * 8, kBlock, 0, st>>>(s->d);
+    k_zero_counters<<<1, 256, 0, st>>>(s->C);
+    VBH_LAUNCHED();
+    s->seq = 0;
+    s->last_frame = 0;
+    return VBH_OK;
+}
+}  // namespace vbh
 
 extern "C" {
 
@@ -1062,37 +1049,7 @@ int vbh_integrate_frame(vbh_scene *s, const float *d_depth, const uint8_t *d_rgb
     if (!s || !d_depth || !pose_c2w || frame_id == 0 || frame_id <= s->last_frame) return VBH_EINVAL;
     for (int i = 0; i < 12; ++i)
         if (!std::isfinite(pose_c2w[i])) return VBH_EINVAL;
-    hipStream_t st = as_stream(stream);
-    const Frame fr = make_frame(s, pose_c2w);
-    const int seq = s->seq;
-    std::array<hipEvent_t, 5> ev{};
-    if (s->timing) {
-        if (s->ev_free.empty()) {
-            for (auto &e : ev) VBH_HIP(hipEventCreate(&e));
-        } else {
-            ev = s->ev_free.back();
-            s->ev_free.pop_back();
-        }
-        s->ev_pending.push_back(ev);
-    }
-    auto mark = [&](int i) { return s->timing ? hipEventRecord(ev[i], st) : hipSuccess; };
-    dim3 ga(unsigned((s->p.width + 31) / 32), unsigned((s->p.height + 8 * (kAllocThreads / 256) - 1) /
-                                                        (8 * (kAllocThreads / 256))));
-    const unsigned g = unsigned(s->cus) * 8;
-    const unsigned gi = unsigned(s->cus) * 8;
-    VBH_HIP(mark(0));
-    k_alloc<<<ga, kAllocThreads, 0, st>>>(s->d, fr, d_depth, frame_id, seq);
-    VBH_HIP(mark(1));
-    k_integrate<<<gi, kBlock, 0, st>>>(s->d, fr, d_depth, d_rgb, seq);
-    VBH_HIP(mark(2));
-    k_mc_mark<<<unsigned(s->cus) * 2, kMarkThreads, 0, st>>>(s->d, frame_id, seq);
-    VBH_HIP(mark(3));
-    k_mc_extract<<<g / 2, kBlock, 0, st>>>(s->d, seq, int(gi));
-    VBH_HIP(mark(4));
-    VBH_LAUNCHED();
-    s->seq = seq + 1;
-    s->last_frame = frame_id;
-    return VBH_OK;
+    return vbh::scene_fuse(s, d_depth, d_rgb, pose_c2w, frame_id, true, as_stream(stream));
 }
 
 int vbh_extract_mc_indices(vbh_scene *s, const int32_t *d_keys, int64_t n, uint8_t *d_mc, uint8_t *d_rgb,

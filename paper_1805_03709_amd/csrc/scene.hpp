@@ -1,0 +1,105 @@
+// Scene state shared by the fusion kernels (scene.hip) and the differentiable form
+// (diff.hip): device layout of a block-hashed TSDF volume with its MC voxel pool and
+// update log, the per-frame camera constants, and the host-side handle.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <vector>
+
+#include "device.hpp"
+#include "host.hpp"
+#include "vbh.h"
+
+namespace vbh {
+
+int table_init(Slot *T, uint64_t n, hipStream_t st);
+
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / 64;
+constexpr int kChunk = 2048;  // log entries per workgroup chunk in the paged walk
+constexpr int kRing = 8;      // per-frame counter ring
+constexpr int kMaxPartials = 1 << 16;
+// Same-address atomics serialise in L2 (about 10 ns each), so every kernel claims list
+// space and reports statistics once per workgroup, never once per wave.
+
+struct FrameCounters {
+    unsigned int n_touched;
+    unsigned int n_new;
+    unsigned int pad0;
+    unsigned int pad1;
+    unsigned long long voxel_updates;
+    unsigned long long log_base;  // log length when the update started; the update's MC
+                                  // list is its log segment [log_base, log_len)
+};
+
+struct Counters {
+    FrameCounters fc[kRing];
+    unsigned long long pool_next;  // pool blocks handed out (may exceed capacity)
+    unsigned long long log_len;    // log entries written or attempted
+    unsigned long long tot_touched;  // sums over all updates so far
+    unsigned long long tot_mc;
+    unsigned long long tot_voxel_updates;
+    uint32_t err;
+    uint32_t pad[7];
+};
+
+// Device view of a scene, passed by value to kernels.
+struct Dev {
+    Slot *T;
+    uint64_t mask;
+    int kind;
+    float *F;            // [P][512]
+    uint32_t *WRGB;      // [P][512] W | R<<8 | G<<16 | B<<24
+    uint32_t *MCV;       // [P][512] index | R<<8 | G<<16 | B<<24
+    uint64_t *pool_key;  // [P]
+    uint32_t *mc_stamp;  // [P]
+    int32_t *touched;    // [slots] slot indices
+    int32_t *mclist;     // [P] pool indices
+    uint64_t *log;       // [L] (frame << 32) | pool
+    int64_t *prefix;     // [max_chunks + 1] scratch of the paged walk
+    unsigned long long *partial;  // [kMaxPartials] per-workgroup statistics, reduced later
+    int64_t pool_cap;
+    uint64_t log_cap;
+    Counters *C;
+};
+
+// Camera, pose and volume constants of one frame.
+struct Frame {
+    float P[12];  // camera-to-world, row-major [R|t]
+    float fx, fy, cx, cy;
+    int W, H;
+    float dmin, dmax;
+    float vs, mu;
+    int m_band;
+};
+
+}  // namespace vbh
+
+// Host-side handle of a scene.
+struct vbh_scene {
+    vbh_params p{};
+    int m_band = 0;
+    vbh::Dev d{};
+    vbh::Counters *C = nullptr;
+    unsigned long long *hostbuf = nullptr;  // device staging for counters
+    int64_t max_chunks = 0;
+    int seq = 0;        // number of updates so far (ring index of the next one)
+    int cus = 256;      // compute units of the device the scene lives on
+    uint32_t last_frame = 0;
+    void *mem[13] = {};
+    bool timing = false;
+    std::vector<std::array<hipEvent_t, 5>> ev_pending, ev_free;
+};
+
+
+namespace vbh {
+// Camera/volume constants for one frame with pose `pose` (row-major 3x4, camera to world).
+Frame make_frame(const vbh_scene *s, const float *pose);
+// Enqueues band allocation and integration of one frame (and, if with_mc, the MC update
+// and log) as update `frame` of the scene; the caller validated the arguments.
+int scene_fuse(vbh_scene *s, const float *d_depth, const uint8_t *d_rgb, const float *pose, uint32_t frame,
+               bool with_mc, hipStream_t st);
+// Empties the scene (table, used pool blocks, stamps, log, counters) on `st`.
+int scene_reset(vbh_scene *s, hipStream_t st);
+}  // namespace vbh
