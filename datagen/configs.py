@@ -38,7 +38,7 @@ TINY_VOL = Volume(slots=1 << 16, pool_blocks=1 << 15, voxel_size=0.01, trunc=0.0
                   depth_min=0.0, depth_max=float("inf"), log_capacity=1 << 20)
 FULL_VOL = Volume(slots=1 << 22, pool_blocks=1 << 21, voxel_size=0.005, trunc=0.02,
                   depth_min=0.4, depth_max=4.0, log_capacity=1 << 26)
-DIFF_VOL = Volume(slots=1 << 20, pool_blocks=1 << 18, voxel_size=0.02, trunc=0.08,
+DIFF_VOL = Volume(slots=1 << 20, pool_blocks=1 << 16, voxel_size=0.02, trunc=0.08,
                   depth_min=0.4, depth_max=4.0, log_capacity=1 << 20)
 
 
@@ -77,10 +77,10 @@ def full_inputs(frames, device="cpu", seed: int = 5203, cam: Camera = FULL_CAM):
 def diff_inputs(device="cpu", n_samples: int = 100_000, seed: int = 4242, first: int = 500,
                 n_frames: int = 16, cam: Camera = FULL_CAM):
     """16 consecutive frames of the full trajectory and K pixel samples drawn uniformly
-    without replacement from their valid pixels: returns (scene, depth, rgb, poses,
+    without replacement from their valid pixels (depth inside the volume's range): returns (scene, depth, rgb, poses,
     sample_frame int32 [K], sample_pixel int32 [K] = v*W+u)."""
     scene, depth, rgb, poses = full_inputs(range(first, first + n_frames), device=device)
-    valid = (depth > 0).reshape(-1).cpu().numpy()
+    valid = ((depth >= DIFF_VOL.depth_min) & (depth <= DIFF_VOL.depth_max)).reshape(-1).cpu().numpy()
     idx = np.flatnonzero(valid)
     rng = np.random.default_rng(seed)
     pick = np.sort(rng.choice(idx, size=min(n_samples, idx.size), replace=False))

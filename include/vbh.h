@@ -206,6 +206,36 @@ int vbh_scene_write_blocks(vbh_scene *s, const int32_t *d_keys, int64_t n, const
 int vbh_scene_enable_timing(vbh_scene *s, int32_t enable);
 int vbh_scene_timing(vbh_scene *s, double *ms_out, int64_t *h_frames, void *stream);
 
+/* ============================================================ differentiable form
+ * Not part of the paper's system: a differentiable variant of the fusion path.  n_frames
+ * depth maps (H x W, float32, in d_depth [n_frames][H][W]) are integrated, with the rules
+ * of vbh_integrate_frame (weight 1 per observation, no colour), into a fresh volume with
+ * the scene parameters p.  K pixel samples (frame index, pixel index v*W+u) are
+ * back-projected, x_k = T_f (D_f[p_k] K^-1 [u, v, 1]), and
+ *     L = sum_k F_tri(x_k)^2,
+ * F_tri being the trilinear interpolation of F over the voxel lattice (voxel g at g *
+ * voxel_size).  Samples whose 8 corner voxels are not all allocated and observed are
+ * dropped (f_samples = NaN).  The backward pass returns dL/dD for every pixel and dL/dxi
+ * for every frame, xi = (rho; phi) being a left perturbation T_f <- Exp(xi) T_f of the
+ * camera-to-world pose; discrete decisions (allocation, pixel of each voxel, skip and
+ * clamp branches, trilinear cells, the sample mask) are those of the forward point and
+ * are not differentiated.  h_poses: host float32 [n_frames][12] (row-major 3x4). */
+typedef struct vbh_diff vbh_diff;
+
+/* n_frames in [1, 32].  Owns a scene created with p. */
+int vbh_diff_create(const vbh_params *p, int32_t n_frames, vbh_diff **out);
+void vbh_diff_destroy(vbh_diff *d);
+/* d_f_samples: float32 [K] (may be NULL); d_loss: float32 scalar on the device. */
+int vbh_diff_forward(vbh_diff *d, const float *d_depth, const float *h_poses, const int32_t *d_sample_frame,
+                     const int32_t *d_sample_pixel, int64_t n_samples, float *d_f_samples, float *d_loss,
+                     void *stream);
+/* Must follow a forward with the same inputs.  d_grad_loss: device float32 scalar dL_out/dL;
+ * outputs (overwritten): d_grad_depth float32 [n_frames][H][W], d_grad_xi float32
+ * [n_frames][6]. */
+int vbh_diff_backward(vbh_diff *d, const float *d_depth, const float *h_poses, const int32_t *d_sample_frame,
+                      const int32_t *d_sample_pixel, int64_t n_samples, const float *d_grad_loss,
+                      float *d_grad_depth, float *d_grad_xi, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -6,7 +6,7 @@
 //
 // Frozen branches: every discrete decision - the band blocks, each voxel's pixel, its
 // validity, the -trunc skip and the +trunc clamp, each sample's trilinear cell and the
-// mask of samples whose eight corners are observed - is taken once, in float32 in the
+// mask of samples with a valid depth whose eight corners are observed - is taken once, in float32 in the
 // written operation order, from the unperturbed inputs.  Values are float64:
 //   F_v = (1/n_v) sum_{f observes v} tsdf_f(v),  tsdf = D_f[pix] - z_f(v) (or trunc if
 //   clamped), z_f(v) = r3_f . (X_v - t_f) with T_f = Exp(xi_f) T0_f (xi = (rho; phi));
@@ -292,6 +292,8 @@ void *orc_diff_new(const orc_diff_problem *prob) {
     d->corner.resize(size_t(K));
     d->keep.assign(size_t(K), 0);
     for (int64_t k = 0; k < K; ++k) {
+        const int fk = d->sf[size_t(k)];
+        if (fk < 0 || fk >= d->F || !valid_depth(d->D(fk)[d->sp[size_t(k)]], p)) continue;  // dropped
         int64_t b[3];
         sample_cell(*d, k, b);
         d->base[size_t(k)] = {b[0], b[1], b[2]};

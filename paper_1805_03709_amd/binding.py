@@ -79,6 +79,10 @@ SIGNATURES = {
     "vbh_scene_write_blocks": ([_V, _P, _I64, _P, _P, _P, C.c_uint32, _V], C.c_int),
     "vbh_scene_enable_timing": ([_V, _I32], C.c_int),
     "vbh_scene_timing": ([_V, C.POINTER(C.c_double), C.POINTER(_I64), _V], C.c_int),
+    "vbh_diff_create": ([C.POINTER(vbh_params), _I32, C.POINTER(_V)], C.c_int),
+    "vbh_diff_destroy": ([_V], None),
+    "vbh_diff_forward": ([_V, _P, C.POINTER(C.c_float), _P, _P, _I64, _P, _P, _V], C.c_int),
+    "vbh_diff_backward": ([_V, _P, C.POINTER(C.c_float), _P, _P, _I64, _P, _P, _P, _V], C.c_int),
 }
 STAGES = ("alloc", "integrate", "mc_mark", "mc_extract")
 

@@ -19,9 +19,6 @@ using namespace vbh;
 
 namespace {
 
-__device__ __forceinline__ bool depth_valid(float d, const Frame &f) {
-    return d > 0.0f && d >= f.dmin && d <= f.dmax;
-}
 
 // Blocks in the MC update set of the update whose counters are fc (valid once its
 // marking has finished): the length of its log segment.

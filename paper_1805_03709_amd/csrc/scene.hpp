@@ -74,6 +74,11 @@ struct Frame {
     int m_band;
 };
 
+// The depth validity rule: positive and inside [dmin, dmax] (float32 tests).
+__device__ __forceinline__ bool depth_valid(float d, const Frame &f) {
+    return d > 0.0f && d >= f.dmin && d <= f.dmax;
+}
+
 }  // namespace vbh
 
 // Host-side handle of a scene.
