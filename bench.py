@@ -112,6 +112,39 @@ def hash_bench(vbh, log_phases=True):
     return out
 
 
+def diff_bench(vbh, reps=5):
+    """Differentiable form on 16 frames of the 640x480 sequence (2 cm voxels, 8 cm
+    truncation, 100k samples): forward and backward kernel time (torch events on the
+    stream the library launches on)."""
+    import torch
+    from datagen import configs
+    from paper_1805_03709_amd.autograd import DiffFusion
+    _, depth, _, poses, sf, sp = configs.diff_inputs(device="cuda")
+    E = DiffFusion(vbh.make_params(configs.DIFF_VOL, configs.FULL_CAM), depth.shape[0])
+    d = depth.contiguous()
+    f = torch.as_tensor(sf).cuda()
+    p = torch.as_tensor(sp).cuda()
+    one = torch.ones((), device="cuda")
+    E.vbh_diff_forward(d, poses, f, p)  # warm-up
+    E.vbh_diff_backward(d, poses, f, p, one)
+    torch.cuda.synchronize()
+    fw, bw = [], []
+    for _ in range(reps):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record()
+        loss, _ = E.vbh_diff_forward(d, poses, f, p, with_samples=False)
+        e[1].record()
+        E.vbh_diff_backward(d, poses, f, p, one)
+        e[2].record()
+        torch.cuda.synchronize()
+        fw.append(e[0].elapsed_time(e[1]))
+        bw.append(e[1].elapsed_time(e[2]))
+    fwd, bwd = sorted(fw)[reps // 2], sorted(bw)[reps // 2]
+    n = depth.shape[0]
+    return {"frames": n, "samples": int(f.numel()), "forward_ms": fwd, "backward_ms": bwd,
+            "backward_ms_per_frame": bwd / n, "backward_over_forward": bwd / fwd, "loss": float(loss)}
+
+
 def cpu_baseline(depth, rgb, traj, budget_s):
     """The oracle, as it stands, on the first frames of the same sequence until the time
     budget is spent (host copies excluded)."""
@@ -140,6 +173,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-hash", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-diff", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (scale reference for HBM counters)")
@@ -200,6 +234,10 @@ def main():
     if not args.no_hash:
         log("[bench] hash map phase")
         result["hash_mops"] = hash_bench(vbh)
+    if not args.no_diff:
+        log("[bench] differentiable form")
+        result["diff"] = diff_bench(vbh)
+        log(f"[bench] diff: {result['diff']}")
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
         d2, c2, t2 = stage_frames(200, "cuda")

@@ -197,6 +197,13 @@ int vbh_scene_read_blocks(vbh_scene *s, const int32_t *d_keys, int64_t n, float 
 int vbh_scene_write_blocks(vbh_scene *s, const int32_t *d_keys, int64_t n, const float *d_F, const uint8_t *d_W,
                            const uint8_t *d_rgb, uint32_t frame_id, void *stream);
 
+/* Synchronising check, then enqueues a copy of log entries [start, start + n) (which must
+ * lie below the log length): d_frame uint32 [n] update frame ids, d_keys int32 [n][3]
+ * block keys (either may be NULL).  The log is append-only, so it is the full history of
+ * MC updates: entry (f, B) is the latest update of B as of version V iff no later entry of
+ * B has a frame <= V. */
+int vbh_scene_log_entries(vbh_scene *s, uint64_t start, int64_t n, uint32_t *d_frame, int32_t *d_keys, void *stream);
+
 /* Stage timing.  When enabled, vbh_integrate_frame records a HIP event pair around each
  * of its kernels on the caller's stream (band allocation, integration, MC update-set
  * marking, MC extraction).  vbh_scene_timing synchronises the stream and returns, per
@@ -205,6 +212,68 @@ int vbh_scene_write_blocks(vbh_scene *s, const int32_t *d_keys, int64_t n, const
 #define VBH_N_STAGES 4
 int vbh_scene_enable_timing(vbh_scene *s, int32_t enable);
 int vbh_scene_timing(vbh_scene *s, double *ms_out, int64_t *h_frames, void *stream);
+
+/* ================================================================= serving loop
+ * Streams MC voxel blocks to exploration clients (Sec. 4.2: per-client streaming state,
+ * requests answered with at most the client's request-size limit; Sec. 4.3: the client
+ * controls request rate and size).  Each client has a cursor into the update log; a
+ * request returns, in log order, up to `limit` blocks whose log entry after the cursor is
+ * live (vbh_updated_blocks_since) with their keys and 512 MC voxels each (uint32 index |
+ * R<<8 | G<<16 | B<<24), and advances the cursor.  A new or reconnecting client starts at
+ * cursor 0 and so receives every block.
+ * vbh_server_run replays a request schedule in real time: a request is admitted when its
+ * arrival time has passed, its client has no request in flight, a request slot is free
+ * and its result fits in the device arena; admitted requests are launched in rounds on a
+ * pool of streams, overlapping with earlier rounds.  Frames given to it are fused at their
+ * times on another stream; a frame's MC update waits until the requests in flight have
+ * completed and no request is launched while it runs, so every request is served against
+ * one scene version (result identical to running it alone at that version).
+ * While a server runs, the scene must not be used through other entry points. */
+typedef struct vbh_server vbh_server;
+
+typedef struct vbh_server_config {
+    int64_t arena_bytes; /* device memory for results in flight, >= 4096 */
+    int32_t max_inflight; /* request slots, 1..4096 */
+    int32_t n_streams;   /* serving streams, 1..8 (default priority) */
+    int32_t n_clients;   /* client table size, >= 1 */
+    int32_t max_batch;   /* requests per launch round, 1..256 */
+} vbh_server_config;
+
+typedef struct vbh_request {
+    int32_t client;
+    int32_t reserved;
+    int64_t limit;       /* request size limit in blocks, >= 0 */
+    double arrival_s;    /* seconds after the start of vbh_server_run; non-decreasing */
+    int32_t *d_keys_out; /* optional device copy of the result keys [limit][3] */
+    uint32_t *d_mc_out;  /* optional device copy of the MC voxels [limit][512] */
+} vbh_request;
+
+typedef struct vbh_request_result {
+    double arrival_s, admit_s, done_s; /* seconds after the start; done = results in memory */
+    int64_t count;                     /* blocks returned */
+    uint64_t cursor_in, cursor_out;    /* client cursor before and after */
+    uint32_t version;                  /* frame id of the scene version served */
+    int32_t status;                    /* VBH_OK, or an error for this request */
+} vbh_request_result;
+
+typedef struct vbh_frame_feed {
+    const float *d_depth;  /* [H*W] */
+    const uint8_t *d_rgb;  /* [H*W*3] or NULL */
+    float pose_c2w[12];
+    double time_s;         /* fuse at this time (seconds after the start) */
+    uint32_t frame_id;     /* increasing, greater than the scene's last frame */
+    uint32_t reserved;
+} vbh_frame_feed;
+
+int vbh_server_create(vbh_scene *scene, const vbh_server_config *cfg, vbh_server **out);
+void vbh_server_destroy(vbh_server *srv);
+/* Client cursor (0 = reconnect: everything again). */
+int vbh_server_set_cursor(vbh_server *srv, int32_t client, uint64_t cursor);
+int vbh_server_get_cursor(vbh_server *srv, int32_t client, uint64_t *cursor);
+/* Blocks until every request is answered and every frame fused.  results: host array of
+ * n_req entries in request order. */
+int vbh_server_run(vbh_server *srv, const vbh_request *reqs, int64_t n_req, const vbh_frame_feed *frames,
+                   int64_t n_frames, vbh_request_result *results);
 
 /* ============================================================ differentiable form
  * Not part of the paper's system: a differentiable variant of the fusion path.  n_frames

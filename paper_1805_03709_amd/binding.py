@@ -49,6 +49,27 @@ class vbh_stats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class vbh_server_config(C.Structure):
+    _fields_ = [("arena_bytes", C.c_int64), ("max_inflight", C.c_int32), ("n_streams", C.c_int32),
+                ("n_clients", C.c_int32), ("max_batch", C.c_int32)]
+
+
+class vbh_request(C.Structure):
+    _fields_ = [("client", C.c_int32), ("reserved", C.c_int32), ("limit", C.c_int64), ("arrival_s", C.c_double),
+                ("d_keys_out", C.c_void_p), ("d_mc_out", C.c_void_p)]
+
+
+class vbh_request_result(C.Structure):
+    _fields_ = [("arrival_s", C.c_double), ("admit_s", C.c_double), ("done_s", C.c_double),
+                ("count", C.c_int64), ("cursor_in", C.c_uint64), ("cursor_out", C.c_uint64),
+                ("version", C.c_uint32), ("status", C.c_int32)]
+
+
+class vbh_frame_feed(C.Structure):
+    _fields_ = [("d_depth", C.c_void_p), ("d_rgb", C.c_void_p), ("pose_c2w", C.c_float * 12),
+                ("time_s", C.c_double), ("frame_id", C.c_uint32), ("reserved", C.c_uint32)]
+
+
 _V, _I64, _U64, _I32, _P = C.c_void_p, C.c_int64, C.c_uint64, C.c_int32, C.c_void_p
 SIGNATURES = {
     "vbh_strerror": ([C.c_int], C.c_char_p),
@@ -79,6 +100,13 @@ SIGNATURES = {
     "vbh_scene_write_blocks": ([_V, _P, _I64, _P, _P, _P, C.c_uint32, _V], C.c_int),
     "vbh_scene_enable_timing": ([_V, _I32], C.c_int),
     "vbh_scene_timing": ([_V, C.POINTER(C.c_double), C.POINTER(_I64), _V], C.c_int),
+    "vbh_scene_log_entries": ([_V, _U64, _I64, _P, _P, _V], C.c_int),
+    "vbh_server_create": ([_V, C.POINTER(vbh_server_config), C.POINTER(_V)], C.c_int),
+    "vbh_server_destroy": ([_V], None),
+    "vbh_server_set_cursor": ([_V, _I32, _U64], C.c_int),
+    "vbh_server_get_cursor": ([_V, _I32, C.POINTER(_U64)], C.c_int),
+    "vbh_server_run": ([_V, C.POINTER(vbh_request), _I64, C.POINTER(vbh_frame_feed), _I64,
+                        C.POINTER(vbh_request_result)], C.c_int),
     "vbh_diff_create": ([C.POINTER(vbh_params), _I32, C.POINTER(_V)], C.c_int),
     "vbh_diff_destroy": ([_V], None),
     "vbh_diff_forward": ([_V, _P, C.POINTER(C.c_float), _P, _P, _I64, _P, _P, _V], C.c_int),
@@ -291,6 +319,13 @@ class Scene:
                "vbh_scene_read_blocks")
         return F, W, rgb, found
 
+    def vbh_scene_log_entries(self, start: int, n: int, device="cuda"):
+        fr = torch.empty(max(n, 1), dtype=torch.int32, device=device)
+        keys = torch.empty((max(n, 1), 3), dtype=torch.int32, device=device)
+        _check(lib().vbh_scene_log_entries(self.h, start, n, _ptr(fr), _ptr(keys), _stream()),
+               "vbh_scene_log_entries")
+        return fr[:n], keys[:n]
+
     def vbh_scene_enable_timing(self, enable: bool = True):
         _check(lib().vbh_scene_enable_timing(self.h, 1 if enable else 0), "vbh_scene_enable_timing")
 
@@ -307,3 +342,62 @@ class Scene:
                                             _ptr(W, torch.uint8, 512 * n, "W"),
                                             _ptr(rgb, torch.uint8, 1536 * n, "rgb"), frame_id, _stream()),
                "vbh_scene_write_blocks")
+
+
+class Server:
+    """Serving loop over a scene (vbh_server_*)."""
+
+    def __init__(self, scene: Scene, arena_bytes: int, max_inflight: int = 256, n_streams: int = 4,
+                 n_clients: int = 64, max_batch: int = 64):
+        self.cfg = vbh_server_config(arena_bytes, max_inflight, n_streams, n_clients, max_batch)
+        h = C.c_void_p()
+        _check(lib().vbh_server_create(scene.h, C.byref(self.cfg), C.byref(h)), "vbh_server_create")
+        self.h, self.scene = h, scene
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().vbh_server_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def vbh_server_set_cursor(self, client: int, cursor: int):
+        _check(lib().vbh_server_set_cursor(self.h, client, cursor), "vbh_server_set_cursor")
+
+    def vbh_server_get_cursor(self, client: int) -> int:
+        c = C.c_uint64()
+        _check(lib().vbh_server_get_cursor(self.h, client, C.byref(c)), "vbh_server_get_cursor")
+        return c.value
+
+    def vbh_server_run(self, clients, limits, arrivals, outputs=None, frames=None):
+        """clients/limits/arrivals: sequences (arrivals non-decreasing, seconds).  outputs:
+        optional list of (keys int32 [limit,3], mc int32 [limit,512]) device tensors per
+        request.  frames: optional list of (depth, rgb or None, pose 3x4, time_s, frame_id).
+        Returns a numpy structured array of results."""
+        n = len(clients)
+        reqs = (vbh_request * max(n, 1))()
+        for i in range(n):
+            reqs[i].client, reqs[i].limit, reqs[i].arrival_s = int(clients[i]), int(limits[i]), float(arrivals[i])
+            if outputs is not None and outputs[i] is not None:
+                k, m = outputs[i]
+                reqs[i].d_keys_out = _ptr(k, torch.int32, 3 * int(limits[i]))
+                reqs[i].d_mc_out = _ptr(m, torch.int32, 512 * int(limits[i]))
+        frames = frames or []
+        feed = (vbh_frame_feed * max(len(frames), 1))()
+        for i, (d, c, pose, t, fid) in enumerate(frames):
+            feed[i].d_depth = _ptr(d, torch.float32)
+            feed[i].d_rgb = _ptr(c, torch.uint8) if c is not None else None
+            P = torch.as_tensor(pose, dtype=torch.float64).reshape(-1)[:12]
+            for j in range(12):
+                feed[i].pose_c2w[j] = float(P[j])
+            feed[i].time_s, feed[i].frame_id = float(t), int(fid)
+        res = (vbh_request_result * max(n, 1))()
+        torch.cuda.synchronize()
+        _check(lib().vbh_server_run(self.h, reqs, n, feed, len(frames), res), "vbh_server_run")
+        import numpy as np
+        dt = np.dtype([(f, np.float64 if t is C.c_double else np.int64) for f, t in vbh_request_result._fields_])
+        out = np.zeros(n, dt)
+        for i in range(n):
+            for f, _ in vbh_request_result._fields_:
+                out[f][i] = getattr(res[i], f)
+        return out

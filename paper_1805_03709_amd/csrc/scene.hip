@@ -840,6 +840,21 @@ __global__ void k_read_counters(const Counters *C, int seq, unsigned long long *
 
 __global__ void k_clear_err(Counters *C) { C->err = 0; }
 
+__global__ void __launch_bounds__(kBlock) k_log_entries(Dev S, uint64_t start, int64_t n, uint32_t *frame,
+                                                        int32_t *keys) {
+    for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock) {
+        const uint64_t e = S.log[start + uint64_t(i)];
+        if (frame) frame[i] = uint32_t(e >> 32);
+        if (keys) {
+            int32_t x, y, z;
+            unpack_key(S.pool_key[uint32_t(e)], x, y, z);
+            keys[3 * i] = x;
+            keys[3 * i + 1] = y;
+            keys[3 * i + 2] = z;
+        }
+    }
+}
+
 // Zeroes the voxel, MC and stamp state of every handed-out pool block, then the counters.
 __global__ void __launch_bounds__(kBlock) k_reset_blocks(Dev S) {
     const unsigned long long pn = S.C->pool_next;
@@ -960,6 +975,16 @@ int scene_fuse(vbh_scene *s, const float *d_depth, const uint8_t *d_rgb, const f
     VBH_LAUNCHED();
     s->seq = seq + 1;
     s->last_frame = frame;
+    return VBH_OK;
+}
+
+int scene_mc_update(vbh_scene *s, uint32_t frame, hipStream_t st) {
+    const int seq = s->seq - 1;
+    if (seq < 0) return VBH_EINVAL;
+    const unsigned g = unsigned(s->cus) * 8;
+    k_mc_mark<<<unsigned(s->cus) * 2, kMarkThreads, 0, st>>>(s->d, frame, seq);
+    k_mc_extract<<<g / 2, kBlock, 0, st>>>(s->d, seq, int(g));
+    VBH_LAUNCHED();
     return VBH_OK;
 }
 
@@ -1141,6 +1166,21 @@ int vbh_scene_write_blocks(vbh_scene *s, const int32_t *d_keys, int64_t n, const
     if (int rc = mc_update(s, frame_id, seq, st)) return rc;
     s->seq = seq + 1;
     s->last_frame = frame_id;
+    return VBH_OK;
+}
+
+int vbh_scene_log_entries(vbh_scene *s, uint64_t start, int64_t n, uint32_t *d_frame, int32_t *d_keys,
+                          void *stream) {
+    if (!s || n < 0) return VBH_EINVAL;
+    unsigned long long h[10];
+    hipStream_t st = as_stream(stream);
+    if (int rc = read_counters(s, s->seq > 0 ? s->seq - 1 : 0, h, st)) return rc;
+    const uint64_t end = h[5] < uint64_t(s->p.log_capacity) ? h[5] : uint64_t(s->p.log_capacity);
+    if (start > end || uint64_t(n) > end - start) return VBH_EINVAL;
+    if (n > 0) {
+        k_log_entries<<<grid_for(n, kBlock, 4096), kBlock, 0, st>>>(s->d, start, n, d_frame, d_keys);
+        VBH_LAUNCHED();
+    }
     return VBH_OK;
 }
 

@@ -105,6 +105,9 @@ Frame make_frame(const vbh_scene *s, const float *pose);
 // and log) as update `frame` of the scene; the caller validated the arguments.
 int scene_fuse(vbh_scene *s, const float *d_depth, const uint8_t *d_rgb, const float *pose, uint32_t frame,
                bool with_mc, hipStream_t st);
+// Enqueues the MC update (update-set marking, MC voxels, stamps, log) of the scene's last
+// update, which must have been fused with with_mc = false as update `frame`.
+int scene_mc_update(vbh_scene *s, uint32_t frame, hipStream_t st);
 // Empties the scene (table, used pool blocks, stamps, log, counters) on `st`.
 int scene_reset(vbh_scene *s, hipStream_t st);
 }  // namespace vbh

@@ -1,0 +1,598 @@
+// Serving loop for exploration clients (Sec. 4.2-4.3): the scene stays resident on the
+// device; clients ask for the MC voxel blocks updated since their last request (at most
+// `limit` blocks, the client-chosen request size); requests are admitted as request slots
+// and result memory free up and are launched in rounds on a pool of streams, so work of
+// requests admitted at different times overlaps on the device (continuous batching);
+// depth frames keep being fused concurrently on another stream.
+//
+// Consistency: a request is served against one scene version V (the last fully published
+// MC update).  A frame's allocation and integration run concurrently with serving, but its
+// MC update (which rewrites MC voxels, stamps and appends to the log) waits behind a gate
+// until the requests in flight have completed, and no request is launched while it runs.
+// So every result equals the result of the same request run alone at version V.
+//
+// Per request, against the log prefix [0, end_V): the live entries after the client's
+// cursor are counted per chunk, the chunk counts are scanned, the first `limit` live
+// entries are emitted in log order, and each selected block's key and its 512 MC voxels
+// (index | R<<8 | G<<16 | B<<24, the 4-byte MC voxel) are gathered into the request's
+// slice of the result arena.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "scene.hpp"
+
+using namespace vbh;
+
+namespace {
+
+constexpr int kSvChunk = 2048;  // log entries per counting workgroup
+constexpr int kSvWG = 256;
+constexpr int kMaxBatch = 256;
+
+// Device descriptor of one admitted request (byte offsets into the arena).
+struct SvReq {
+    uint64_t cursor;     // first log position to consider
+    uint64_t end;        // log end of the request's scene version
+    int64_t limit;
+    int64_t chunk_base;  // first counting item of this request in the round
+    int64_t n_chunks;
+    int64_t item_base;   // first gather item (prefix of limits) in the round
+    int64_t off_sel;     // int32 [limit] selected pool indices
+    int64_t off_cnt;     // int64 [n_chunks] chunk counts, then exclusive prefixes
+    int64_t off_keys;    // int32 [limit][3]
+    int64_t off_mc;      // uint32 [limit][512]
+    int64_t off_meta;    // int64 count, uint64 next cursor
+};
+
+struct SvRound {
+    const SvReq *req;
+    int n;
+    int64_t total_chunks;
+    int64_t total_items;
+    char *arena;
+};
+
+__device__ __forceinline__ int find_req(const SvRound &R, int64_t item, bool by_chunk) {
+    int lo = 0, hi = R.n - 1;  // last request whose base <= item
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const int64_t b = by_chunk ? R.req[mid].chunk_base : R.req[mid].item_base;
+        if (b <= item) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ bool entry_live(const Dev &S, uint64_t pos, uint64_t end) {
+    if (pos >= end) return false;
+    const uint64_t e = S.log[pos];
+    return S.mc_stamp[uint32_t(e)] == uint32_t(e >> 32);
+}
+
+__global__ void __launch_bounds__(kSvWG) k_sv_count(Dev S, SvRound R) {
+    __shared__ int part[kSvWG / 64];
+    for (int64_t it = blockIdx.x; it < R.total_chunks; it += gridDim.x) {
+        const int r = find_req(R, it, true);
+        const SvReq q = R.req[r];
+        const int64_t c = it - q.chunk_base;
+        int cnt = 0;
+        for (int k = 0; k < kSvChunk / kSvWG; ++k)
+            cnt += entry_live(S, q.cursor + uint64_t(c) * kSvChunk + uint64_t(k) * kSvWG + threadIdx.x, q.end);
+        cnt = wave_sum(cnt);
+        if (lane_id() == 0) part[threadIdx.x >> 6] = cnt;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int64_t s = 0;
+            for (int w = 0; w < kSvWG / 64; ++w) s += part[w];
+            reinterpret_cast<int64_t *>(R.arena + q.off_cnt)[c] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// One workgroup per request: exclusive scan of its chunk counts, count and (when fewer
+// than `limit` live entries exist) the next cursor.
+__global__ void __launch_bounds__(kSvWG) k_sv_scan(SvRound R) {
+    __shared__ int64_t part[kSvWG];
+    const SvReq q = R.req[blockIdx.x];
+    int64_t *cnt = reinterpret_cast<int64_t *>(R.arena + q.off_cnt);
+    const int64_t per = (q.n_chunks + kSvWG - 1) / kSvWG;
+    const int64_t lo = threadIdx.x * per, hi = lo + per < q.n_chunks ? lo + per : q.n_chunks;
+    int64_t s = 0;
+    for (int64_t c = lo; c < hi; ++c) s += cnt[c];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 1; o < kSvWG; o <<= 1) {
+        const int64_t v = threadIdx.x >= o ? part[threadIdx.x - o] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int64_t run = part[threadIdx.x] - s;
+    for (int64_t c = lo; c < hi; ++c) {
+        const int64_t v = cnt[c];
+        cnt[c] = run;
+        run += v;
+    }
+    if (threadIdx.x == kSvWG - 1) {
+        const int64_t total = part[kSvWG - 1];
+        int64_t *meta = reinterpret_cast<int64_t *>(R.arena + q.off_meta);
+        meta[0] = total < q.limit ? total : q.limit;
+        if (q.limit == 0) meta[1] = int64_t(q.cursor);
+        else if (total < q.limit) meta[1] = int64_t(q.end);
+    }
+}
+
+__global__ void __launch_bounds__(kSvWG) k_sv_emit(Dev S, SvRound R) {
+    __shared__ int wc[kSvWG / 64];
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    for (int64_t it = blockIdx.x; it < R.total_chunks; it += gridDim.x) {
+        const int r = find_req(R, it, true);
+        const SvReq q = R.req[r];
+        const int64_t c = it - q.chunk_base;
+        int64_t rank = reinterpret_cast<const int64_t *>(R.arena + q.off_cnt)[c];
+        if (rank >= q.limit) continue;  // uniform per workgroup
+        int32_t *sel = reinterpret_cast<int32_t *>(R.arena + q.off_sel);
+        int64_t *meta = reinterpret_cast<int64_t *>(R.arena + q.off_meta);
+        for (int k = 0; k < kSvChunk / kSvWG; ++k) {
+            const uint64_t pos = q.cursor + uint64_t(c) * kSvChunk + uint64_t(k) * kSvWG + threadIdx.x;
+            const bool live = entry_live(S, pos, q.end);
+            const unsigned long long m = __ballot(live);
+            if (lane == 0) wc[wave] = __popcll(m);
+            __syncthreads();
+            int64_t before = rank, total = 0;
+            for (int w = 0; w < kSvWG / 64; ++w) {
+                if (w < wave) before += wc[w];
+                total += wc[w];
+            }
+            const int64_t rr = before + lanes_below(m);
+            if (live && rr < q.limit) {
+                sel[rr] = int32_t(uint32_t(S.log[pos]));
+                if (rr == q.limit - 1) meta[1] = int64_t(pos + 1);
+            }
+            rank += total;
+            __syncthreads();
+        }
+    }
+}
+
+// One wave per selected block: its key and 512 MC voxels into the arena.
+__global__ void __launch_bounds__(kSvWG) k_sv_gather(Dev S, SvRound R) {
+    const int lane = lane_id();
+    const int64_t gw = int64_t(blockIdx.x) * (kSvWG / 64) + (threadIdx.x >> 6);
+    const int64_t nw = int64_t(gridDim.x) * (kSvWG / 64);
+    for (int64_t it = gw; it < R.total_items; it += nw) {
+        const int r = find_req(R, it, false);
+        const SvReq q = R.req[r];
+        const int64_t b = it - q.item_base;
+        const int64_t count = reinterpret_cast<const int64_t *>(R.arena + q.off_meta)[0];
+        if (b >= count) continue;
+        const int32_t pool = reinterpret_cast<const int32_t *>(R.arena + q.off_sel)[b];
+        const uint4 *src = reinterpret_cast<const uint4 *>(S.MCV + int64_t(pool) * 512);
+        uint4 *dst = reinterpret_cast<uint4 *>(R.arena + q.off_mc) + b * 128;
+        dst[lane] = src[lane];
+        dst[lane + 64] = src[lane + 64];
+        if (lane < 3) {
+            int32_t k[3];
+            unpack_key(S.pool_key[pool], k[0], k[1], k[2]);
+            reinterpret_cast<int32_t *>(R.arena + q.off_keys)[b * 3 + lane] = k[lane];
+        }
+    }
+}
+
+__global__ void k_sv_read_log_len(const Counters *C, unsigned long long *out, uint64_t cap) {
+    const unsigned long long L = C->log_len;
+    out[0] = L < cap ? L : cap;
+}
+
+using Clock = std::chrono::steady_clock;
+
+// First-fit allocator of arena byte ranges (256-byte aligned) with coalescing.
+struct Arena {
+    std::map<int64_t, int64_t> free_;  // offset -> size
+    void init(int64_t bytes) { free_ = {{0, bytes}}; }
+    int64_t alloc(int64_t n) {
+        n = (n + 255) & ~int64_t(255);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= n) {
+                const int64_t off = it->first, rest = it->second - n;
+                free_.erase(it);
+                if (rest) free_[off + n] = rest;
+                return off;
+            }
+        }
+        return -1;
+    }
+    void release(int64_t off, int64_t n) {
+        n = (n + 255) & ~int64_t(255);
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+}  // namespace
+
+struct vbh_server {
+    vbh_scene *scene = nullptr;
+    vbh_server_config cfg{};
+    char *arena = nullptr;
+    Arena alloc;
+    std::vector<hipStream_t> streams;
+    hipStream_t istream = nullptr;
+    SvReq *d_desc = nullptr;    // [max_inflight][max_batch] device descriptors, one row per round
+    SvReq *h_desc = nullptr;    // pinned staging for the same (a row is reused only after its
+                                // round completed, so its upload has been consumed)
+    int64_t *h_meta = nullptr;  // pinned [max_inflight][2] results copied back
+    unsigned long long *d_len = nullptr, *h_len = nullptr;
+    std::vector<uint64_t> cursor;  // per client
+    uint64_t end_v = 0;            // log end of the published version
+    uint32_t version = 0;
+};
+
+namespace {
+
+struct InFlight {
+    int64_t req;
+    int64_t off, bytes;
+    int slot;
+};
+
+struct RoundRec {
+    hipEvent_t ev;
+    int stream;
+    int row;  // descriptor row
+    std::vector<InFlight> items;
+};
+
+double secs(Clock::time_point t0) { return std::chrono::duration<double>(Clock::now() - t0).count(); }
+
+int64_t req_bytes(int64_t limit, int64_t n_chunks) {
+    auto al = [](int64_t n) { return (n + 255) & ~int64_t(255); };
+    return al(limit * 4) + al(n_chunks * 8) + al(limit * 12) + al(limit * 2048) + 256;
+}
+
+int read_log_end(vbh_server *v, hipStream_t st, uint64_t *out) {
+    k_sv_read_log_len<<<1, 1, 0, st>>>(v->scene->C, v->d_len, uint64_t(v->scene->p.log_capacity));
+    VBH_LAUNCHED();
+    VBH_HIP(hipMemcpyAsync(v->h_len, v->d_len, 8, hipMemcpyDeviceToHost, st));
+    VBH_HIP(hipStreamSynchronize(st));
+    *out = v->h_len[0];
+    return VBH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vbh_server_create(vbh_scene *scene, const vbh_server_config *cfg, vbh_server **out) {
+    if (!out || !scene || !cfg || cfg->arena_bytes < 4096 || cfg->max_inflight < 1 || cfg->max_inflight > 4096 ||
+        cfg->n_streams < 1 || cfg->n_streams > 8 || cfg->n_clients < 1 || cfg->max_batch < 1 ||
+        cfg->max_batch > kMaxBatch || int64_t(cfg->max_inflight) * cfg->max_batch > (int64_t(1) << 18))
+        return VBH_EINVAL;
+    *out = nullptr;
+    vbh_server *v = new (std::nothrow) vbh_server();
+    if (!v) return VBH_ENOMEM;
+    v->scene = scene;
+    v->cfg = *cfg;
+    v->cursor.assign(size_t(cfg->n_clients), 0);
+    bool ok = hipMalloc(&v->arena, size_t(cfg->arena_bytes)) == hipSuccess &&
+              hipMalloc(&v->d_desc, sizeof(SvReq) * size_t(cfg->max_batch) * cfg->max_inflight) == hipSuccess &&
+              hipHostMalloc(&v->h_desc, sizeof(SvReq) * size_t(cfg->max_batch) * cfg->max_inflight) == hipSuccess &&
+              hipHostMalloc(&v->h_meta, 16 * size_t(cfg->max_inflight)) == hipSuccess &&
+              hipMalloc(&v->d_len, 8) == hipSuccess && hipHostMalloc(&v->h_len, 8) == hipSuccess;
+    for (int i = 0; ok && i < cfg->n_streams; ++i) {
+        hipStream_t s;
+        ok = hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
+        if (ok) v->streams.push_back(s);
+    }
+    ok = ok && hipStreamCreateWithFlags(&v->istream, hipStreamNonBlocking) == hipSuccess;
+    if (!ok) {
+        vbh_server_destroy(v);
+        return VBH_ENOMEM;
+    }
+    v->alloc.init(cfg->arena_bytes);
+    if (read_log_end(v, v->istream, &v->end_v) != VBH_OK) {
+        vbh_server_destroy(v);
+        return VBH_EHIP;
+    }
+    v->version = scene->last_frame;
+    *out = v;
+    return VBH_OK;
+}
+
+void vbh_server_destroy(vbh_server *v) {
+    if (!v) return;
+    for (hipStream_t s : v->streams) {
+        (void)hipStreamSynchronize(s);
+        (void)hipStreamDestroy(s);
+    }
+    if (v->istream) {
+        (void)hipStreamSynchronize(v->istream);
+        (void)hipStreamDestroy(v->istream);
+    }
+    if (v->arena) (void)hipFree(v->arena);
+    if (v->d_desc) (void)hipFree(v->d_desc);
+    if (v->h_desc) (void)hipHostFree(v->h_desc);
+    if (v->h_meta) (void)hipHostFree(v->h_meta);
+    if (v->d_len) (void)hipFree(v->d_len);
+    if (v->h_len) (void)hipHostFree(v->h_len);
+    delete v;
+}
+
+int vbh_server_set_cursor(vbh_server *v, int32_t client, uint64_t cursor) {
+    if (!v || client < 0 || client >= v->cfg.n_clients) return VBH_EINVAL;
+    v->cursor[size_t(client)] = cursor;
+    return VBH_OK;
+}
+
+int vbh_server_get_cursor(vbh_server *v, int32_t client, uint64_t *cursor) {
+    if (!v || !cursor || client < 0 || client >= v->cfg.n_clients) return VBH_EINVAL;
+    *cursor = v->cursor[size_t(client)];
+    return VBH_OK;
+}
+
+int vbh_server_run(vbh_server *v, const vbh_request *reqs, int64_t n_req, const vbh_frame_feed *frames,
+                   int64_t n_frames, vbh_request_result *res) {
+    if (!v || n_req < 0 || n_frames < 0 || (n_req > 0 && (!reqs || !res)) || (n_frames > 0 && !frames))
+        return VBH_EINVAL;
+    for (int64_t i = 0; i < n_req; ++i) {
+        if (reqs[i].client < 0 || reqs[i].client >= v->cfg.n_clients || reqs[i].limit < 0 ||
+            (i > 0 && reqs[i].arrival_s < reqs[i - 1].arrival_s))
+            return VBH_EINVAL;
+        res[i] = vbh_request_result{};
+        res[i].status = 1;  // pending
+    }
+    vbh_scene *sc = v->scene;
+    const auto t0 = Clock::now();
+    // --- gate between serving and the MC update of fused frames
+    std::mutex mu;
+    std::condition_variable cv;
+    bool mc_request = false, mc_granted = false;
+    std::atomic<int> int_error{VBH_OK};
+    std::atomic<bool> int_done{n_frames == 0};
+    std::thread integ([&]() {
+        for (int64_t f = 0; f < n_frames; ++f) {
+            const vbh_frame_feed &fr = frames[f];
+            while (secs(t0) < fr.time_s) std::this_thread::sleep_for(std::chrono::microseconds(50));
+            if (!fr.d_depth || fr.frame_id <= sc->last_frame) {
+                int_error = VBH_EINVAL;
+                break;
+            }
+            int rc = scene_fuse(sc, fr.d_depth, fr.d_rgb, fr.pose_c2w, fr.frame_id, false, v->istream);
+            if (rc == VBH_OK) rc = hipStreamSynchronize(v->istream) == hipSuccess ? VBH_OK : VBH_EHIP;
+            if (rc != VBH_OK) {
+                int_error = rc;
+                break;
+            }
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                mc_request = true;
+                cv.wait(lk, [&] { return mc_granted; });
+            }
+            rc = scene_mc_update(sc, fr.frame_id, v->istream);
+            uint64_t end = 0;
+            if (rc == VBH_OK) rc = read_log_end(v, v->istream, &end);
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                if (rc == VBH_OK) {
+                    v->end_v = end;
+                    v->version = fr.frame_id;
+                }
+                mc_request = false;
+                mc_granted = false;
+            }
+            cv.notify_all();
+            if (rc != VBH_OK) {
+                int_error = rc;
+                break;
+            }
+        }
+        int_done = true;
+        std::lock_guard<std::mutex> lk(mu);
+        mc_request = false;
+        cv.notify_all();
+    });
+
+    // --- scheduler (this thread)
+    std::vector<std::deque<int64_t>> queue(size_t(v->cfg.n_clients));
+    std::vector<char> busy(size_t(v->cfg.n_clients), 0);
+    std::vector<int> free_slots, free_rows;
+    for (int i = v->cfg.max_inflight - 1; i >= 0; --i) {
+        free_slots.push_back(i);
+        free_rows.push_back(i);
+    }
+    std::deque<RoundRec> rounds;
+    std::vector<std::vector<RoundRec>> dummy;
+    std::vector<hipEvent_t> ev_pool;
+    int64_t next_arrival = 0, n_done = 0;
+    int next_stream = 0;
+    int rc_all = VBH_OK;
+    const int64_t cap_chunks_per_req = (sc->p.log_capacity + kSvChunk - 1) / kSvChunk + 1;
+    while (n_done < n_req && rc_all == VBH_OK) {
+        const double now = secs(t0);
+        while (next_arrival < n_req && reqs[next_arrival].arrival_s <= now) {
+            queue[size_t(reqs[next_arrival].client)].push_back(next_arrival);
+            ++next_arrival;
+        }
+        bool gate = false;
+        uint64_t end_v;
+        uint32_t ver;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            gate = mc_request;
+            end_v = v->end_v;
+            ver = v->version;
+            if (mc_request && !mc_granted && rounds.empty()) {
+                mc_granted = true;
+                cv.notify_all();
+            }
+        }
+        // admit and launch one round
+        if (!gate && !free_rows.empty()) {
+            const int si = next_stream;
+            const int row = free_rows.back();
+            SvReq *hd = v->h_desc + int64_t(row) * v->cfg.max_batch;
+            RoundRec rr;
+            rr.stream = si;
+            rr.row = row;
+            int64_t chunks = 0, items = 0;
+            for (int c = 0; c < v->cfg.n_clients && int(rr.items.size()) < v->cfg.max_batch; ++c) {
+                if (busy[size_t(c)] || queue[size_t(c)].empty() || free_slots.empty()) continue;
+                const int64_t ri = queue[size_t(c)].front();
+                const uint64_t cur = v->cursor[size_t(c)];
+                const int64_t lim = reqs[ri].limit;
+                const int64_t nch = cur < end_v ? int64_t((end_v - cur + kSvChunk - 1) / kSvChunk) : 0;
+                const int64_t bytes = req_bytes(lim, nch);
+                if (nch > cap_chunks_per_req || bytes > v->cfg.arena_bytes) {
+                    res[ri].status = VBH_EINVAL;  // can never fit
+                    queue[size_t(c)].pop_front();
+                    ++n_done;
+                    continue;
+                }
+                const int64_t off = v->alloc.alloc(bytes);
+                if (off < 0) continue;  // admitted later, when memory frees up
+                queue[size_t(c)].pop_front();
+                busy[size_t(c)] = 1;
+                const int slot = free_slots.back();
+                free_slots.pop_back();
+                SvReq &q = hd[rr.items.size()];
+                auto al = [](int64_t n) { return (n + 255) & ~int64_t(255); };
+                q.cursor = cur;
+                q.end = end_v;
+                q.limit = lim;
+                q.chunk_base = chunks;
+                q.n_chunks = nch;
+                q.item_base = items;
+                q.off_sel = off;
+                q.off_cnt = q.off_sel + al(lim * 4);
+                q.off_keys = q.off_cnt + al(nch * 8);
+                q.off_mc = q.off_keys + al(lim * 12);
+                q.off_meta = q.off_mc + al(lim * 2048);
+                chunks += nch;
+                items += lim;
+                res[ri].arrival_s = reqs[ri].arrival_s;
+                res[ri].admit_s = now;
+                res[ri].cursor_in = cur;
+                res[ri].version = ver;
+                rr.items.push_back({ri, off, bytes, slot});
+            }
+            if (!rr.items.empty()) {
+                free_rows.pop_back();
+                hipStream_t st = v->streams[size_t(si)];
+                SvReq *dd = v->d_desc + int64_t(row) * v->cfg.max_batch;
+                const int n = int(rr.items.size());
+                int e = hipMemcpyAsync(dd, hd, sizeof(SvReq) * size_t(n), hipMemcpyHostToDevice, st) != hipSuccess;
+                SvRound R{dd, n, chunks, items, v->arena};
+                const unsigned gc = unsigned(std::min<int64_t>(std::max<int64_t>(chunks, 1), int64_t(sc->cus) * 8));
+                const unsigned gg =
+                    unsigned(std::min<int64_t>(std::max<int64_t>((items + 3) / 4, 1), int64_t(sc->cus) * 16));
+                if (chunks > 0) k_sv_count<<<gc, kSvWG, 0, st>>>(sc->d, R);
+                k_sv_scan<<<unsigned(n), kSvWG, 0, st>>>(R);
+                if (chunks > 0) k_sv_emit<<<gc, kSvWG, 0, st>>>(sc->d, R);
+                if (items > 0) k_sv_gather<<<gg, kSvWG, 0, st>>>(sc->d, R);
+                e |= hipGetLastError() != hipSuccess;
+                for (int i = 0; i < n; ++i) {
+                    const InFlight &f = rr.items[size_t(i)];
+                    const vbh_request &q = reqs[f.req];
+                    e |= hipMemcpyAsync(v->h_meta + 2 * f.slot, v->arena + hd[i].off_meta, 16, hipMemcpyDeviceToHost,
+                                        st) != hipSuccess;
+                    if (q.d_keys_out && q.limit > 0)
+                        e |= hipMemcpyAsync(q.d_keys_out, v->arena + hd[i].off_keys, size_t(q.limit) * 12,
+                                            hipMemcpyDeviceToDevice, st) != hipSuccess;
+                    if (q.d_mc_out && q.limit > 0)
+                        e |= hipMemcpyAsync(q.d_mc_out, v->arena + hd[i].off_mc, size_t(q.limit) * 2048,
+                                            hipMemcpyDeviceToDevice, st) != hipSuccess;
+                }
+                if (ev_pool.empty()) {
+                    hipEvent_t ev;
+                    e |= hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess;
+                    ev_pool.push_back(ev);
+                }
+                rr.ev = ev_pool.back();
+                ev_pool.pop_back();
+                e |= hipEventRecord(rr.ev, st) != hipSuccess;
+                if (e) {
+                    rc_all = VBH_EHIP;
+                    break;
+                }
+                rounds.push_back(std::move(rr));
+                next_stream = (next_stream + 1) % v->cfg.n_streams;
+            }
+        }
+        // completions (rounds on one stream finish in order; poll all)
+        for (auto it = rounds.begin(); it != rounds.end();) {
+            const hipError_t q = hipEventQuery(it->ev);
+            if (q == hipErrorNotReady) {
+                ++it;
+                continue;
+            }
+            if (q != hipSuccess) {
+                rc_all = VBH_EHIP;
+                break;
+            }
+            const double tdone = secs(t0);
+            for (const InFlight &f : it->items) {
+                const int64_t *m = v->h_meta + 2 * f.slot;
+                vbh_request_result &r = res[f.req];
+                r.count = m[0];
+                r.cursor_out = uint64_t(m[1]);
+                r.done_s = tdone;
+                r.status = VBH_OK;
+                const int c = reqs[f.req].client;
+                v->cursor[size_t(c)] = r.cursor_out;
+                busy[size_t(c)] = 0;
+                v->alloc.release(f.off, f.bytes);
+                free_slots.push_back(f.slot);
+                ++n_done;
+            }
+            ev_pool.push_back(it->ev);
+            free_rows.push_back(it->row);
+            it = rounds.erase(it);
+        }
+        if (int_error != VBH_OK) rc_all = int_error;
+        std::this_thread::yield();
+    }
+    // drain outstanding GPU work and let integration finish its schedule
+    for (hipStream_t s : v->streams) (void)hipStreamSynchronize(s);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        rounds.clear();
+    }
+    while (!int_done) {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            if (mc_request && !mc_granted) {
+                mc_granted = true;
+                cv.notify_all();
+            }
+        }
+        std::this_thread::sleep_for(std::chrono::microseconds(50));
+    }
+    integ.join();
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    if (rc_all == VBH_OK && int_error != VBH_OK) rc_all = int_error;
+    return rc_all;
+}
+
+}  // extern "C"
