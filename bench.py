@@ -145,6 +145,62 @@ def diff_bench(vbh, reps=5):
             "backward_ms_per_frame": bwd / n, "backward_over_forward": bwd / fwd, "loss": float(loss)}
 
 
+def serve_bench(vbh, seconds=60.0, warmup=10.0, clients=64, rate=30.0, n_unique_frames=600):
+    """Serving: ~2M-block scene resident on the device, `clients` clients with Poisson
+    arrivals (`rate` req/s each), request sizes floor(10^U(2,5)) blocks, every client
+    starting from cursor 0, while 640x480 frames are fused at 30 Hz.  Latency = arrival to
+    results in device memory; statistics over requests arriving after the warm-up."""
+    import numpy as np
+    import torch
+    from datagen import configs
+    t0 = time.time()
+    scene = configs.serve_scene()
+    keys, F, W, rgb = configs.analytic_blocks(scene, configs.SERVE_VOL.voxel_size, configs.SERVE_VOL.trunc,
+                                              device="cuda")
+    S = vbh.Scene(vbh.make_params(configs.SERVE_VOL, configs.FULL_CAM))
+    S.vbh_scene_write_blocks(keys.contiguous(), F.contiguous(), W.contiguous(), rgb.contiguous(), 1)
+    st = S.vbh_scene_stats()
+    if S.vbh_scene_status() != 0:
+        raise RuntimeError("serving scene load failed")
+    del F, W, rgb
+    log(f"[bench] serve scene: {st['n_blocks']} blocks, log {st['log_length']} ({time.time() - t0:.1f}s)")
+    depth, rgbf, traj = configs.serve_frames(n_unique_frames, device="cuda")
+    total = seconds + warmup
+    nf = int(total * 30)
+    frames = [(depth[f % n_unique_frames], rgbf[f % n_unique_frames], traj[f % n_unique_frames], f / 30.0, f + 2)
+              for f in range(nf)]
+    rng = np.random.default_rng(6464)
+    arr, cl = [], []
+    for c in range(clients):
+        t = np.cumsum(rng.exponential(1.0 / rate, int(total * rate * 1.5) + 50))
+        t = t[t < total]
+        arr.append(t)
+        cl.append(np.full(t.size, c))
+    arr, cl = np.concatenate(arr), np.concatenate(cl)
+    order = np.argsort(arr, kind="stable")
+    arr, cl = arr[order], cl[order]
+    lim = np.floor(10 ** rng.uniform(2, 5, arr.size)).astype(np.int64)
+    srv = vbh.Server(S, arena_bytes=24 << 30, max_inflight=512, n_streams=4, n_clients=clients, max_batch=64)
+    log(f"[bench] serving {arr.size} requests over {total:.0f}s with {nf} fused frames")
+    res = srv.vbh_server_run(cl, lim, arr, frames=frames)
+    if (res["status"] != 0).any() or S.vbh_scene_status() != 0:
+        raise RuntimeError("serving reported an error")
+    m = res["arrival_s"] >= warmup
+    lat = (res["done_s"] - res["arrival_s"])[m] * 1e3
+    queue = (res["admit_s"] - res["arrival_s"])[m] * 1e3
+    blocks = res["count"][m].sum()
+    span = res["done_s"][m].max() - warmup
+    out = {"requests": int(m.sum()), "clients": clients, "rate_per_client": rate, "seconds": seconds,
+           "scene_blocks": int(st["n_blocks"]), "frames_fused": nf,
+           "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+           "p50_queue_ms": float(np.percentile(queue, 50)), "p99_queue_ms": float(np.percentile(queue, 99)),
+           "blocks_per_s": float(blocks / span), "MB_per_s": float(blocks * 2060 / span / 1e6),
+           "versions_served": int(np.unique(res["version"][m]).size)}
+    srv.close()
+    S.close()
+    return out
+
+
 def cpu_baseline(depth, rgb, traj, budget_s):
     """The oracle, as it stands, on the first frames of the same sequence until the time
     budget is spent (host copies excluded)."""
@@ -174,6 +230,8 @@ def main():
     ap.add_argument("--no-hash", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-diff", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (scale reference for HBM counters)")
@@ -238,6 +296,10 @@ def main():
         log("[bench] differentiable form")
         result["diff"] = diff_bench(vbh)
         log(f"[bench] diff: {result['diff']}")
+    if not args.no_serve:
+        log("[bench] serving")
+        result["serve"] = serve_bench(vbh, seconds=args.serve_seconds)
+        log(f"[bench] serve: {result['serve']}")
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
         d2, c2, t2 = stage_frames(200, "cuda")

@@ -38,6 +38,8 @@ TINY_VOL = Volume(slots=1 << 16, pool_blocks=1 << 15, voxel_size=0.01, trunc=0.0
                   depth_min=0.0, depth_max=float("inf"), log_capacity=1 << 20)
 FULL_VOL = Volume(slots=1 << 22, pool_blocks=1 << 21, voxel_size=0.005, trunc=0.02,
                   depth_min=0.4, depth_max=4.0, log_capacity=1 << 26)
+SERVE_VOL = Volume(slots=1 << 23, pool_blocks=1 << 22, voxel_size=0.005, trunc=0.02,
+                   depth_min=0.4, depth_max=4.0, log_capacity=1 << 26)
 DIFF_VOL = Volume(slots=1 << 20, pool_blocks=1 << 16, voxel_size=0.02, trunc=0.08,
                   depth_min=0.4, depth_max=4.0, log_capacity=1 << 20)
 
@@ -88,6 +90,24 @@ def diff_inputs(device="cpu", n_samples: int = 100_000, seed: int = 4242, first:
     return scene, depth, rgb, poses, (pick // hw).astype(np.int32), (pick % hw).astype(np.int32)
 
 
+def serve_scene(seed: int = 6464):
+    """20x20x3 m room of 80 boxes and 40 spheres: about 2M blocks at 5 mm voxels."""
+    return room_of_boxes_scene(seed, SERVE_VOL.voxel_size, size=(20.0, 20.0, 3.0), n_boxes=80, n_spheres=40)
+
+
+def serve_frames(n_unique: int, device="cpu", seed: int = 6464, cam: Camera = FULL_CAM):
+    """n_unique noisy 640x480 frames (depth, RGB, poses) along a random walk in the serving
+    scene; callers cycle through them to fuse frames at 30 Hz."""
+    scene = serve_scene(seed)
+    traj = trajectory_c3(scene, n_unique, seed)
+    depth = torch.empty((n_unique, cam.height, cam.width), dtype=torch.float32, device=device)
+    rgb = torch.empty((n_unique, cam.height, cam.width, 3), dtype=torch.uint8, device=device)
+    for f in range(n_unique):
+        d, c = render_frames(scene, cam, [traj[f]], device=device, noise_seed=seed, first_frame=f)
+        depth[f], rgb[f] = d[0], c[0]
+    return depth, rgb, traj
+
+
 def analytic_blocks(scene, voxel_size: float, trunc: float, device="cpu", seed: int = 6464,
                     chunk: int = 1 << 16):
     """Every 8^3 block whose centre lies within trunc + half the block diagonal of the
@@ -116,8 +136,9 @@ def analytic_blocks(scene, voxel_size: float, trunc: float, device="cpu", seed: 
         p = gv.to(torch.float64) * voxel_size
         F[s:s + chunk] = scene_sdf(scene, p).clamp(-trunc, trunc).to(torch.float32)
     W = torch.as_tensor(rng.integers(1, 256, size=(keys.shape[0], 512), dtype=np.uint8), device=device)
-    gv = keys.to(torch.int64)[:, None, :] * 8 + lvox[None]
-    cell = gv.sum(-1).remainder(2)
-    grey = torch.where(cell > 0, 200, 90).to(torch.uint8)
-    rgb = torch.stack([grey, grey, (grey // 2 + 60).to(torch.uint8)], -1)
+    rgb = torch.empty(keys.shape[0], 512, 3, dtype=torch.uint8, device=device)
+    for s in range(0, keys.shape[0], chunk):
+        gv = keys[s:s + chunk].to(torch.int64)[:, None, :] * 8 + lvox[None]
+        grey = torch.where(gv.sum(-1).remainder(2) > 0, 200, 90).to(torch.uint8)
+        rgb[s:s + chunk] = torch.stack([grey, grey, (grey // 2 + 60).to(torch.uint8)], -1)
     return keys, F, W, rgb
