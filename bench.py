@@ -44,6 +44,23 @@ def stage_frames(K, device):
     return depth, rgb, traj
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary (FETCH_SIZE
+    and WRITE_SIZE scaled by a plain-copy calibration), or None if the kernel source changed
+    since the counters were taken."""
+    import hashlib
+    try:
+        t = json.load(open(os.path.join(ROOT, "profiles", "fusion_full_traffic.json")))
+        src = open(os.path.join(ROOT, "paper_1805_03709_amd", "csrc", "scene.hip"), "rb").read()
+    except OSError:
+        return None
+    if hashlib.sha1(src).hexdigest() != t.get("scene_hip_sha1") or ("k_" + kernel) not in t["per_dispatch"]:
+        return None
+    d = t["per_dispatch"]["k_" + kernel]
+    return {"fetch_bytes": d["fetch_MB"] * 1e6, "write_bytes": d["write_MB"] * 1e6,
+            "bytes": (d["fetch_MB"] + d["write_MB"]) * 1e6, "workload": t["workload"]}
+
+
 def run_fusion(vbh, depth, rgb, traj, K, W):
     import torch
     from datagen import configs
@@ -281,7 +298,10 @@ def main():
                                "2 cm truncation, 2^22 slots, 2^21-block pool, per-frame MC update",
                    "frames": K, "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": (measured_traffic(dom) or {}).get("bytes"),
+                     "traffic_detail": measured_traffic(dom),
+                     "algorithmic_bytes_per_launch": bytes_stage[dom] / K},
         "stages": per_stage,
         "scene": {"blocks": stats["n_blocks"], "touched_per_frame": stats["total_touched"] / K,
                   "mc_blocks_per_frame": stats["total_mc"] / K,
