@@ -204,13 +204,14 @@ int vbh_scene_write_blocks(vbh_scene *s, const int32_t *d_keys, int64_t n, const
  * B has a frame <= V. */
 int vbh_scene_log_entries(vbh_scene *s, uint64_t start, int64_t n, uint32_t *d_frame, int32_t *d_keys, void *stream);
 
-/* Stage timing.  When enabled, vbh_integrate_frame records a HIP event pair around each
- * of its kernels on the caller's stream (band allocation, integration, MC update-set
- * marking, MC extraction).  vbh_scene_timing synchronises the stream and returns, per
- * stage, the summed kernel milliseconds and the number of frames measured since the
- * last call (then resets).  ms_out must hold VBH_N_STAGES doubles. */
+/* Stage timing.  With period n > 0, every n-th update of vbh_integrate_frame launches its
+ * kernels (band allocation, integration, MC update-set marking, MC extraction) with HIP
+ * start/stop events attached to the kernel dispatches on the caller's stream; period 0
+ * turns timing off (the default).  vbh_scene_timing synchronises the stream and returns,
+ * per stage, the summed kernel milliseconds and the number of updates measured since the
+ * last call (then resets).  ms_out must hold VBH_N_STAGES doubles.  EINVAL for period < 0. */
 #define VBH_N_STAGES 4
-int vbh_scene_enable_timing(vbh_scene *s, int32_t enable);
+int vbh_scene_enable_timing(vbh_scene *s, int32_t period);
 int vbh_scene_timing(vbh_scene *s, double *ms_out, int64_t *h_frames, void *stream);
 
 /* ================================================================= serving loop

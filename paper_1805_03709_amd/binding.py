@@ -326,8 +326,9 @@ class Scene:
                "vbh_scene_log_entries")
         return fr[:n], keys[:n]
 
-    def vbh_scene_enable_timing(self, enable: bool = True):
-        _check(lib().vbh_scene_enable_timing(self.h, 1 if enable else 0), "vbh_scene_enable_timing")
+    def vbh_scene_enable_timing(self, period: int = 1):
+        """Time the kernels of every `period`-th update (0 turns timing off)."""
+        _check(lib().vbh_scene_enable_timing(self.h, int(period)), "vbh_scene_enable_timing")
 
     def vbh_scene_timing(self):
         """{stage: summed kernel ms}, frames measured (synchronising; resets)."""

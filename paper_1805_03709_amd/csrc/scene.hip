@@ -5,6 +5,7 @@
 // the -trunc skip) is computed in IEEE float32 in the operation order written in the
 // comments, with contraction off and correctly rounded division, so its outcome is fully
 // determined by the float32 inputs.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <array>
@@ -62,33 +63,43 @@ __device__ __forceinline__ void stage_put(StageBuf<CAP> &b, bool put, int32_t v)
 }
 
 // ------------------------------------------------------------------ allocation
-// One wave per 8x8 pixel tile; lane = lx + 8 ly.  Each valid pixel takes 2m+1 band
+// One workgroup per 32x16-pixel tile, thread = pixel.  Each valid pixel takes 2m+1 band
 // samples at camera depth lam = (d - mu) + s*vs:
 //   xn = ((float)u - cx) / fx, yn = ((float)v - cy) / fy, pc = (lam*xn, lam*yn, lam),
 //   pw_i = ((R_i0 pc_x + R_i1 pc_y) + R_i2 pc_z) + t_i,  B_i = floor(pw_i / (8 vs)).
-// A sample whose key equals the lane's previous sample or the same sample of the left
-// or upper lane is skipped (that lane handles the key), which removes most duplicate
-// probes before they reach the table.  Samples are processed in groups of kGroup: all
-// keys of a group are formed first, their home slots are read together, then their
-// frame stamps, so a lane keeps several independent loads in flight.  The first thread
-// to raise a block's frame stamp appends the slot to the touched list; appends are
-// gathered per lane and written with one atomic per wave.
-constexpr int kGroup = 5;
-constexpr int kAllocThreads = 512;  // 32x16 pixels: eight 8x8 tiles
+// About a hundred samples of a tile fall into each block, so the keys are first made
+// unique inside the workgroup: a sample whose key equals the pixel's previous sample or
+// the same sample of the left or upper pixel of its 8x8 wave tile is dropped at once, and
+// the rest go into an LDS hash set.  Only the tile's distinct keys then reach the global
+// table, one thread each: its home slot's key and frame stamp are read together, absent
+// keys are claimed with a CAS (and get pool blocks from one reservation per workgroup),
+// and the thread that raises a block's frame stamp appends it to the touched list (one
+// atomic per workgroup, shared with the new-block count).
+constexpr int kAllocThreads = 512;  // 32x16 pixels: eight 8x8 wave tiles
+constexpr int kSetSlots = 2048;     // LDS hash set of keys (load <= 1/2, see kListFlush)
+constexpr int kListCap = 1024;      // distinct keys collected before they are processed
+constexpr int kListFlush = kListCap - kAllocThreads;  // one sample step adds <= 512 keys
+
+__device__ __forceinline__ uint32_t set_hash(uint64_t k) {
+    return uint32_t((k * 0x9E3779B97F4A7C15ull) >> 40);
+}
 
 __global__ void __launch_bounds__(kAllocThreads) k_alloc(Dev S, Frame fr, const float *__restrict__ depth,
                                                          uint32_t frame, int seq) {
-    constexpr int kCap = 2 * kAllocThreads * kGroup;
-    __shared__ StageBuf<kCap> tb;
-    __shared__ unsigned int n_claim, n_new_wg;
+    __shared__ unsigned long long set[kSetSlots];
+    __shared__ unsigned long long list[kListCap];
+    __shared__ int32_t appended[kListCap];
+    __shared__ unsigned int n_list, n_app, n_claim, n_new_wg;
     __shared__ unsigned long long pool_base;
     FrameCounters *fc = &S.C->fc[seq & (kRing - 1)];
     if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) begin_update(S, seq);
+    for (int i = threadIdx.x; i < kSetSlots; i += kAllocThreads) set[i] = kEmpty;
     if (threadIdx.x == 0) {
+        n_list = 0;
+        n_app = 0;
         n_claim = 0;
         n_new_wg = 0;
     }
-    stage_reset(tb);
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
     const int lx = lane & 7, ly = lane >> 3;
@@ -103,15 +114,12 @@ __global__ void __launch_bounds__(kAllocThreads) k_alloc(Dev S, Frame fr, const 
     const float bs = 8.0f * fr.vs;
     const int n_samples = 2 * fr.m_band + 1;
     uint64_t prev = kEmpty;
-    for (int s0 = 0; s0 < n_samples; s0 += kGroup) {
-        uint64_t key[kGroup];
-        uint32_t work = 0;
-#pragma unroll
-        for (int i = 0; i < kGroup; ++i) {
-            const int s = s0 + i;
+    __syncthreads();
+    for (int s = 0; s < n_samples; ++s) {  // workgroup-uniform
+        if (wave_any) {
             const float lam = (d - fr.mu) + float(s) * fr.vs;
-            bool ok = s < n_samples && valid && lam > 0.0f;
-            key[i] = kEmpty;
+            bool ok = valid && lam > 0.0f;
+            uint64_t key = kEmpty;
             if (ok) {
                 const float pc[3] = {lam * xn, lam * yn, lam};
                 int32_t B[3];
@@ -124,118 +132,114 @@ __global__ void __launch_bounds__(kAllocThreads) k_alloc(Dev S, Frame fr, const 
                     B[c] = ok ? int32_t(q) : 0;
                 }
                 if (ok)
-                    key[i] = pack_key(B[0], B[1], B[2]);
+                    key = pack_key(B[0], B[1], B[2]);
                 else
                     raise_err(&S.C->err, kErrKeyRange);
             }
-            const uint64_t left = __shfl(key[i], (lane + 63) & 63);
-            const uint64_t up = __shfl(key[i], (lane + 56) & 63);
-            const bool dup = key[i] == prev || (lx > 0 && key[i] == left) || (ly > 0 && key[i] == up);
-            if (ok && !dup) work |= 1u << i;
-            prev = ok ? key[i] : kEmpty;
-        }
-        int32_t slot[kGroup];
-        uint32_t fresh = 0;
-        unsigned int claim_idx[kGroup];
-#pragma unroll
-        for (int i = 0; i < kGroup; ++i) {
-            slot[i] = -1;
-            claim_idx[i] = 0;
-        }
-        if (wave_any && __ballot(work != 0) != 0) {
-        // home slots, read together
-        uint32_t home[kGroup];
-        uint64_t first[kGroup];
-#pragma unroll
-        for (int i = 0; i < kGroup; ++i) {
-            first[i] = kEmpty;
-            home[i] = 0;
-            if (work & (1u << i)) {
-                int32_t x, y, z;
-                unpack_key(key[i], x, y, z);
-                home[i] = uint32_t(home_slot(x, y, z, key[i], S.kind, S.mask));
-                first[i] = ld_key(S.T + home[i]);
+            const uint64_t left = __shfl(key, (lane + 63) & 63);
+            const uint64_t up = __shfl(key, (lane + 56) & 63);
+            const bool dup = key == prev || (lx > 0 && key == left) || (ly > 0 && key == up);
+            prev = ok ? key : kEmpty;
+            bool fresh = false;
+            if (ok && !dup) {  // insert into the workgroup's set; the inserting thread owns the key
+                uint32_t h = set_hash(key) & (kSetSlots - 1);
+                for (int n = 0; n < kSetSlots; ++n) {
+                    const unsigned long long old = atomicCAS(&set[h], kEmpty, key);
+                    if (old == kEmpty) {
+                        fresh = true;
+                        break;
+                    }
+                    if (old == key) break;
+                    h = (h + 1) & (kSetSlots - 1);
+                }
             }
-        }
-#pragma unroll
-        for (int i = 0; i < kGroup; ++i) {
-            slot[i] = -1;
-            claim_idx[i] = 0;
-            if (!(work & (1u << i))) continue;
-            if (first[i] == key[i]) {
-                slot[i] = int32_t(home[i]);
-                continue;
-            }
-            bool claimed;
-            slot[i] = int32_t(probe_claim(S.T, S.mask, key[i], home[i], claimed));
-            if (slot[i] < 0) raise_err(&S.C->err, kErrTableFull);
-            if (claimed) fresh |= 1u << i;
-        }
-        // claimed keys get workgroup-local indices; their pool blocks are handed out in
-        // one batch after the barrier below (readers do not need the value meanwhile)
-#pragma unroll
-        for (int i = 0; i < kGroup; ++i) {
-            const bool c = (fresh >> i) & 1u;
-            const unsigned long long m = __ballot(c);
+            const unsigned long long m = __ballot(fresh);
             if (m) {
                 const int leader = __builtin_ctzll(m);
                 unsigned int p0 = 0;
-                if (lane == leader) p0 = atomicAdd(&n_claim, unsigned(__popcll(m)));
+                if (lane == leader) p0 = atomicAdd(&n_list, unsigned(__popcll(m)));
                 p0 = __shfl(p0, leader);
-                claim_idx[i] = p0 + unsigned(lanes_below(m));
+                if (fresh) list[p0 + unsigned(lanes_below(m))] = key;
             }
         }
-        // frame stamps, read together; the winner of the stamp race appends
-        uint32_t stamp[kGroup];
-#pragma unroll
-        for (int i = 0; i < kGroup; ++i)
-            stamp[i] = slot[i] >= 0 ? __hip_atomic_load(&S.T[slot[i]].stamp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                                    : frame;
-        uint32_t app = 0;
-#pragma unroll
-        for (int i = 0; i < kGroup; ++i)
-            if (stamp[i] != frame && atomicMax(&S.T[slot[i]].stamp, frame) < frame) app |= 1u << i;
-#pragma unroll
-        for (int i = 0; i < kGroup; ++i) stage_put(tb, (app >> i) & 1u, slot[i]);
-        }  // wave has work
         __syncthreads();
-        if (n_claim) {  // uniform: one pool reservation per workgroup and group
-            if (threadIdx.x == 0) {
-                pool_base = atomicAdd(&S.C->pool_next, (unsigned long long)n_claim);
-                n_new_wg += n_claim;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int i = 0; i < kGroup; ++i) {
-                if (!((fresh >> i) & 1u)) continue;
-                const unsigned long long pool = pool_base + claim_idx[i];
-                if (int64_t(pool) < S.pool_cap) {
-                    S.pool_key[pool] = key[i];
-                    st_val(S.T + slot[i], int32_t(pool));
+        const unsigned int nl = n_list;
+        if (nl <= unsigned(kListFlush) && s + 1 < n_samples) continue;  // uniform
+        // the collected distinct keys against the global table, one thread per key
+        for (unsigned int r = 0; r < nl; r += kAllocThreads) {  // uniform
+            const unsigned int i = r + threadIdx.x;
+            int32_t slot = -1;
+            bool claimed = false, stamp_now = false;
+            uint64_t key = kEmpty;
+            unsigned int cidx = 0;
+            if (i < nl) {
+                key = list[i];
+                int32_t x, y, z;
+                unpack_key(key, x, y, z);
+                const uint32_t home = uint32_t(home_slot(x, y, z, key, S.kind, S.mask));
+                const uint64_t first = ld_key(S.T + home);
+                const uint32_t st = __hip_atomic_load(&S.T[home].stamp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (first == key) {
+                    slot = int32_t(home);
+                    stamp_now = st == frame;  // already touched by this frame
                 } else {
-                    st_val(S.T + slot[i], kNoPool);
-                    raise_err(&S.C->err, kErrPoolFull);
+                    slot = int32_t(probe_claim(S.T, S.mask, key, home, claimed));
+                    if (slot < 0) raise_err(&S.C->err, kErrTableFull);
                 }
+                if (claimed) cidx = atomicAdd(&n_claim, 1u);
             }
             __syncthreads();
-            if (threadIdx.x == 0) n_claim = 0;
-            __syncthreads();
-        }
-        if (tb.count > unsigned(kCap - kAllocThreads * kGroup) || s0 + kGroup >= n_samples) {
-            // one combined 64-bit atomic claims touched-list space and counts new blocks
-            if (threadIdx.x == 0) {
-                const unsigned long long add = (unsigned long long)n_new_wg << 32 | tb.count;
-                const unsigned long long old =
-                    add ? atomicAdd(reinterpret_cast<unsigned long long *>(&fc->n_touched), add) : 0ull;
-                tb.base = old & 0xFFFFFFFFull;
-                n_new_wg = 0;
+            const unsigned int nc = n_claim;
+            if (nc) {  // uniform: one pool reservation per workgroup and round
+                if (threadIdx.x == 0) {
+                    pool_base = atomicAdd(&S.C->pool_next, (unsigned long long)nc);
+                    n_new_wg += nc;
+                }
+                __syncthreads();
+                if (claimed) {
+                    const unsigned long long pool = pool_base + cidx;
+                    if (int64_t(pool) < S.pool_cap) {
+                        S.pool_key[pool] = key;
+                        st_val(S.T + slot, int32_t(pool));
+                    } else {
+                        st_val(S.T + slot, kNoPool);
+                        raise_err(&S.C->err, kErrPoolFull);
+                    }
+                }
+                if (threadIdx.x == 0) n_claim = 0;  // every thread read it before the barrier above
+                __syncthreads();
             }
-            __syncthreads();
-            for (unsigned int i = threadIdx.x; i < tb.count; i += kAllocThreads) S.touched[tb.base + i] = tb.item[i];
-            __syncthreads();
-            if (threadIdx.x == 0) tb.count = 0;
-            __syncthreads();
+            const bool app = slot >= 0 && !stamp_now && atomicMax(&S.T[slot].stamp, frame) < frame;
+            const unsigned long long m = __ballot(app);
+            if (m) {
+                const int leader = __builtin_ctzll(m);
+                unsigned int p0 = 0;
+                if (lane == leader) p0 = atomicAdd(&n_app, unsigned(__popcll(m)));
+                p0 = __shfl(p0, leader);
+                if (app) appended[p0 + unsigned(lanes_below(m))] = slot;
+            }
         }
+        __syncthreads();
+        // touched-list space and the new-block count in one 64-bit atomic
+        if (threadIdx.x == 0) {
+            const unsigned long long add = (unsigned long long)n_new_wg << 32 | n_app;
+            const unsigned long long old =
+                add ? atomicAdd(reinterpret_cast<unsigned long long *>(&fc->n_touched), add) : 0ull;
+            pool_base = old & 0xFFFFFFFFull;  // reused as the list base
+            n_new_wg = 0;
+        }
+        __syncthreads();
+        for (unsigned int i = threadIdx.x; i < n_app; i += kAllocThreads) S.touched[pool_base + i] = appended[i];
+        if (s + 1 < n_samples) {  // start a new collection
+            for (int i = threadIdx.x; i < kSetSlots; i += kAllocThreads) set[i] = kEmpty;
+            prev = kEmpty;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            n_list = 0;
+            n_app = 0;
+        }
+        __syncthreads();
     }
 }
 
@@ -259,6 +263,12 @@ __device__ __forceinline__ void put_log(const Dev &S, const FrameCounters &fc, u
         raise_err(&S.C->err, kErrLogFull);
 }
 
+__device__ __forceinline__ uint64_t first_lane64(uint64_t v) {
+    const uint32_t lo = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(v))));
+    const uint32_t hi = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(v >> 32))));
+    return uint64_t(hi) << 32 | lo;
+}
+
 // ----------------------------------------------------------------- integration
 // One wave per touched block; lane = lx + 8 ly handles voxels (lx, ly, lz), lz = 0..7.
 //   pw_i = (float)g_i * vs, dl_i = pw_i - t_i, pc_j = (R_0j dl_0 + R_1j dl_1) + R_2j dl_2;
@@ -266,14 +276,6 @@ __device__ __forceinline__ void put_log(const Dev &S, const FrameCounters &fc, u
 //   outside the image; skip unless the pixel depth d is valid; sdf = d - pc_z; skip if
 //   sdf < -mu.  Then F <- (W F + min(sdf, mu)) / (W + 1), W <- min(W + 1, 255) and each
 //   colour channel c <- (W c + c_obs + floor(n / 2)) / n with n = W + 1.
-// Exact floor(num / n) for num < 2^17 and 1 <= n <= 256 from a float reciprocal: the
-// float estimate is within one of the quotient, and one correction step fixes it.
-__device__ __forceinline__ uint32_t udiv_small(uint32_t num, uint32_t n, float inv_n) {
-    uint32_t q = uint32_t(float(num) * inv_n);
-    if (q * n > num) --q;
-    else if ((q + 1u) * n <= num) ++q;
-    return q;
-}
 
 // The eight voxels (lx, ly, 0..7) of a lane are projected first, then their depths are
 // loaded together, then the TSDF state (and observed colour) of the passing voxels is
@@ -292,12 +294,14 @@ __global__ void __launch_bounds__(kBlock) k_integrate(Dev S, Frame fr, const flo
     if (gw < n) cur = S.T[S.touched[gw]];
     for (int64_t t = gw; t < n; t += nw) {
         const int32_t next_idx = t + nw < n ? S.touched[t + nw] : -1;
-        const int32_t pool = cur.val;
+        // every lane loaded the same slot: make it wave-uniform (scalar registers)
+        const int32_t pool = __builtin_amdgcn_readfirstlane(cur.val);
         int32_t bx, by, bz;
-        unpack_key(cur.key, bx, by, bz);
+        unpack_key(first_lane64(cur.key), bx, by, bz);
         const float dlx = float(8 * bx + lx) * fr.vs - fr.P[3];
         const float dly = float(8 * by + ly) * fr.vs - fr.P[7];
-        const int64_t base = int64_t(pool) * 512 + lane;
+        float *const Fb = S.F + int64_t(pool) * 512 + lane;
+        uint32_t *const Wb = S.WRGB + int64_t(pool) * 512 + lane;
         int32_t pix[8];
         float pz[8];
 #pragma unroll
@@ -322,6 +326,7 @@ __global__ void __launch_bounds__(kBlock) k_integrate(Dev S, Frame fr, const flo
         bool ok[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) ok[j] = pix[j] >= 0 && depth_valid(d[j], fr) && !(d[j] - pz[j] < -fr.mu);
+        const uint32_t col = pool >= 0 ? S.SGN[int64_t(pool) * 64 + lane] : 0u;  // this lane's column
         float F[8];
         uint32_t w[8];
         uint32_t rg[8], bl[8];
@@ -332,8 +337,8 @@ __global__ void __launch_bounds__(kBlock) k_integrate(Dev S, Frame fr, const flo
             rg[j] = 0u;
             bl[j] = 0u;
             if (ok[j]) {
-                F[j] = S.F[base + 64 * j];
-                w[j] = S.WRGB[base + 64 * j];
+                F[j] = Fb[64 * j];
+                w[j] = Wb[64 * j];
                 if (rgb) {
                     const uint8_t *o = rgb + int64_t(pix[j]) * 3;
                     rg[j] = o[0];
@@ -345,19 +350,27 @@ __global__ void __launch_bounds__(kBlock) k_integrate(Dev S, Frame fr, const flo
         uint32_t Wn[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {  // branch-free: computed for every voxel, stored if ok
+            // n = W + 1 observations (256 once W saturates at 255); 1/n from the hardware
+            // reciprocal (relative error below 2^-22)
             const float tsdf = fminf(d[j] - pz[j], fr.mu);
             const uint32_t w_old = w[j] & 0xFFu;
-            const uint32_t nn = w_old + 1u;
-            Fn[j] = (float(w_old) * F[j] + tsdf) / float(nn);
-            uint32_t out = nn > 255u ? 255u : nn;
+            const float wf = float(w_old);
+            const float inv = __builtin_amdgcn_rcpf(wf + 1.0f);
+            Fn[j] = (wf * F[j] + tsdf) * inv;
+            uint32_t out = w_old == 255u ? 255u : w_old + 1u;
             if (rgb) {
-                const float inv = 1.0f / float(nn);
+                // c <- floor((W c + c_obs + floor(n/2)) / n).  The numerator plus 1/2 is formed
+                // exactly in float (integers below 2^17); its true quotient then lies at least
+                // 1/(2n) >= 1/512 away from an integer, while the product with the reciprocal
+                // is off by at most 256 * 2^-22, so truncation gives the exact floor.
+                const float half = float((w_old + 1u) >> 1) + 0.5f;
                 const uint32_t o3 = rg[j] | bl[j] << 8;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    const uint32_t cur_c = (w[j] >> (8 * (c + 1))) & 0xFFu;
-                    const uint32_t num = w_old * cur_c + ((o3 >> (8 * c)) & 0xFFu) + (nn >> 1);
-                    out |= udiv_small(num, nn, inv) << (8 * (c + 1));
+                    const float cur_c = float((w[j] >> (8 * (c + 1))) & 0xFFu);
+                    const float obs_c = float((o3 >> (8 * c)) & 0xFFu);
+                    const float num = wf * cur_c + (obs_c + half);
+                    out |= uint32_t(num * inv) << (8 * (c + 1));
                 }
             } else {
                 out |= w[j] & 0xFFFFFF00u;
@@ -367,11 +380,20 @@ __global__ void __launch_bounds__(kBlock) k_integrate(Dev S, Frame fr, const flo
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             if (ok[j]) {
-                S.F[base + 64 * j] = Fn[j];
-                S.WRGB[base + 64 * j] = Wn[j];
+                Fb[64 * j] = Fn[j];
+                Wb[64 * j] = Wn[j];
                 ++updates;
             }
         }
+        // updated voxels replace their sign/observed bits (W >= 1 after an update)
+        uint32_t upd = 0, bits = 0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            upd |= uint32_t(ok[j]) * (0x101u << j);
+            bits |= uint32_t(ok[j] && Fn[j] < 0.0f) << j;
+            bits |= uint32_t(ok[j] && Fn[j] == Fn[j]) << (8 + j);
+        }
+        if (upd) S.SGN[int64_t(pool) * 64 + lane] = uint16_t((col & ~upd) | bits);
         cur = nxt;
     }
     __shared__ unsigned long long wg_updates;
@@ -432,114 +454,87 @@ __global__ void __launch_bounds__(kMarkThreads) k_mc_mark(Dev S, uint32_t frame,
 }
 
 // ------------------------------------------------------------- MC extraction
-// One wave per block.  The block and its +x/+y/+z halo (9^3 F values, NaN where W = 0 or
-// the neighbour block is missing) are staged in LDS; each lane then forms the case
-// index of voxels (lx, ly, 0..7) from its 8 corners in Lorensen-Cline order, bit k set
-// iff F(corner k) < 0, index 0 if any corner is NaN, and indices 0 / 255 cut to 0.
-constexpr int kHalo = 729;
+// One wave per block, lane = cell column (x, y), working on the blocks' sign/observed
+// columns rather than on their voxels.  A lane loads the columns (x + dx, y + dy),
+// dx, dy in {0, 1}, from the block or its +x / +y / +x+y neighbours, and the z = 8 bit of
+// each from the +z neighbours; the eight corner bits of its eight cells then come out of
+// one 8x8 bit transpose.  Corners follow the Lorensen-Cline order; a cell with an
+// unobserved corner, or a corner in a missing block, gets index 0; indices 0 and 255 are
+// cut to 0 together with their colour.
 
-__device__ __forceinline__ void wave_sync_lds() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+// 8x8 bit-matrix transpose: bit c of byte r moves to bit r of byte c.
+__device__ __forceinline__ uint64_t transpose8(uint64_t x) {
+    uint64_t t;
+    t = (x ^ (x >> 7)) & 0x00AA00AA00AA00AAull;
+    x = x ^ t ^ (t << 7);
+    t = (x ^ (x >> 14)) & 0x0000CCCC0000CCCCull;
+    x = x ^ t ^ (t << 14);
+    t = (x ^ (x >> 28)) & 0x00000000F0F0F0F0ull;
+    x = x ^ t ^ (t << 28);
+    return x;
 }
 
-// Value staged in the halo: F if the voxel was observed (W > 0), else NaN.
-__device__ __forceinline__ float staged(float f, uint32_t w) { return (w & 0xFFu) ? f : __builtin_nanf(""); }
-
 // Computes the 512 MC voxels of block `pool` (key B) into out[j] for voxel lane + 64 j.
-// Loads are issued in two batches (own block + neighbour probes, then the 217 halo
-// voxels from always-valid addresses) so each wave waits on memory twice per block.
-__device__ __forceinline__ void mc_block(const Dev &S, int32_t pool, uint64_t key, float *halo, uint32_t (&out)[8]) {
+__device__ __forceinline__ void mc_block(const Dev &S, int32_t pool, uint64_t key, uint32_t (&out)[8]) {
     const int lane = lane_id();
-    const int lx = lane & 7, ly = lane >> 3;
-    uint32_t own[8];
-    float fo[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const int64_t idx = int64_t(pool) * 512 + lane + 64 * j;
-        own[j] = S.WRGB[idx];
-        fo[j] = S.F[idx];
-    }
+    const int x = lane & 7, y = lane >> 3;
     int32_t bx, by, bz;
     unpack_key(key, bx, by, bz);
-    int32_t nb = -1;
-    if (lane < 8) {
-        if (lane == 0) {
-            nb = pool;
-        } else {
-            const int32_t nx = bx + (lane & 1), ny = by + ((lane >> 1) & 1), nz = bz + ((lane >> 2) & 1);
-            if (key_ok(nx, ny, nz)) {
-                const uint64_t nk = pack_key(nx, ny, nz);
-                const int64_t ps = probe_locate(S.T, S.mask, nk, home_slot(nx, ny, nz, nk, S.kind, S.mask));
-                if (ps >= 0) nb = S.T[ps].val;
-            }
+    // lane e in 1..7 finds neighbour B + (e & 1, e >> 1 & 1, e >> 2 & 1)
+    int32_t nb = pool;
+    if (lane >= 1 && lane < 8) {
+        nb = -1;
+        const int32_t nx = bx + (lane & 1), ny = by + ((lane >> 1) & 1), nz = bz + ((lane >> 2) & 1);
+        if (key_ok(nx, ny, nz)) {
+            const uint64_t nk = pack_key(nx, ny, nz);
+            const int64_t ps = probe_locate(S.T, S.mask, nk, home_slot(nx, ny, nz, nk, S.kind, S.mask));
+            if (ps >= 0) nb = S.T[ps].val;
         }
     }
     int32_t nbs[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) nbs[e] = __shfl(nb, e);
-    // halo items of this lane: faces x = 8 (from +x, local x = 0), y = 8, z = 8, and for
-    // lanes < 25 one edge/corner voxel; a missing neighbour reads the own block instead
-    // (always valid memory) and is masked to NaN afterwards
-    const int a = lane & 7, b = lane >> 3;
-    int32_t src_blk[4];
-    int src_loc[4], dst[4];
-    src_blk[0] = nbs[1]; src_loc[0] = 8 * a + 64 * b; dst[0] = 8 + 9 * a + 81 * b;
-    src_blk[1] = nbs[2]; src_loc[1] = a + 64 * b;     dst[1] = a + 9 * 8 + 81 * b;
-    src_blk[2] = nbs[4]; src_loc[2] = a + 8 * b;      dst[2] = a + 9 * b + 81 * 8;
-    if (lane < 8) {
-        src_blk[3] = nbs[3]; src_loc[3] = 64 * lane;   dst[3] = 8 + 9 * 8 + 81 * lane;  // +x+y edge
-    } else if (lane < 16) {
-        src_blk[3] = nbs[5]; src_loc[3] = 8 * (lane - 8); dst[3] = 8 + 9 * (lane - 8) + 81 * 8;  // +x+z
-    } else if (lane < 24) {
-        src_blk[3] = nbs[6]; src_loc[3] = lane - 16;   dst[3] = (lane - 16) + 9 * 8 + 81 * 8;  // +y+z
-    } else if (lane == 24) {
-        src_blk[3] = nbs[7]; src_loc[3] = 0;           dst[3] = 8 + 9 * 8 + 81 * 8;         // +x+y+z
-    } else {
-        src_blk[3] = -1; src_loc[3] = 0; dst[3] = -1;
+    for (int e = 0; e < 8; ++e) nbs[e] = __builtin_amdgcn_readlane(nb, e);
+    // columns (x, y), (x + 1, y), (x + 1, y + 1), (x, y + 1): corners 0..3 at z, 4..7 at z + 1
+    uint32_t lo[4], hi[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int xx = x + (c == 1 || c == 2), yy = y + (c >= 2);
+        const int e = (xx >> 3) | ((yy >> 3) << 1);
+        const int o = (xx & 7) + 8 * (yy & 7);
+        const int32_t pl = e == 0 ? nbs[0] : e == 1 ? nbs[1] : e == 2 ? nbs[2] : nbs[3];
+        const int32_t pu = e == 0 ? nbs[4] : e == 1 ? nbs[5] : e == 2 ? nbs[6] : nbs[7];
+        lo[c] = pl >= 0 ? S.SGN[int64_t(pl) * 64 + o] : 0u;
+        hi[c] = pu >= 0 ? S.SGN[int64_t(pu) * 64 + o] : 0u;
     }
-    float hf[4];
-    uint32_t hw[4];
+    uint32_t neg[4], obs[4];  // 9-bit columns, z = 0..8
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int64_t idx = int64_t(src_blk[i] >= 0 ? src_blk[i] : pool) * 512 + src_loc[i];
-        hf[i] = S.F[idx];
-        hw[i] = S.WRGB[idx];
+    for (int c = 0; c < 4; ++c) {
+        neg[c] = (lo[c] & 0xFFu) | (hi[c] & 1u) << 8;
+        obs[c] = (lo[c] >> 8) | ((hi[c] >> 8) & 1u) << 8;
     }
+    // byte k = corner k's bits over the lane's eight cells (bit j = cell z = j)
+    const uint64_t rows = uint64_t((neg[0] & 0xFFu) | (neg[1] & 0xFFu) << 8 | (neg[2] & 0xFFu) << 16 |
+                                   (neg[3] & 0xFFu) << 24) |
+                          uint64_t((neg[0] >> 1) | (neg[1] >> 1) << 8 | (neg[2] >> 1) << 16 | (neg[3] >> 1) << 24)
+                              << 32;
+    const uint64_t idx = transpose8(rows);  // byte j = case index of cell z = j
+    const uint32_t all_obs = obs[0] & obs[1] & obs[2] & obs[3];
+    const uint32_t any_neg = neg[0] | neg[1] | neg[2] | neg[3];
+    const uint32_t all_neg = neg[0] & neg[1] & neg[2] & neg[3];
+    const uint32_t keep = all_obs & (all_obs >> 1) & (any_neg | (any_neg >> 1)) & ~(all_neg & (all_neg >> 1));
+    uint32_t colour[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) halo[lx + 9 * ly + 81 * j] = staged(fo[j], own[j]);
+    for (int j = 0; j < 8; ++j) colour[j] = S.WRGB[int64_t(pool) * 512 + lane + 64 * j];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-        if (dst[i] >= 0) halo[dst[i]] = src_blk[i] >= 0 ? staged(hf[i], hw[i]) : __builtin_nanf("");
-    wave_sync_lds();
-    constexpr int off[8] = {0, 1, 10, 9, 81, 82, 91, 90};
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const int base = lx + 9 * ly + 81 * j;
-        uint32_t idx = 0;
-        bool bad = false;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const float c = halo[base + off[k]];
-            bad |= c != c;
-            idx |= uint32_t(c < 0.0f) << k;
-        }
-        if (bad || idx == 0u || idx == 255u)
-            out[j] = 0u;
-        else
-            out[j] = idx | (own[j] & 0xFFFFFF00u);
-    }
-    wave_sync_lds();  // halo is reused by the next block of this wave
+    for (int j = 0; j < 8; ++j)
+        out[j] = (keep >> j) & 1u ? (uint32_t(idx >> (8 * j)) & 0xFFu) | (colour[j] & 0xFFFFFF00u) : 0u;
 }
 
 // Per-frame form: MC list -> MC pool.
 // Workgroup 0 also folds the integration kernel's n_partials per-workgroup voxel counts
 // into the update's statistics.
 __global__ void __launch_bounds__(kBlock) k_mc_extract(Dev S, int seq, int n_partials) {
-    __shared__ float halo_all[kWaves][kHalo];
     __shared__ unsigned long long red[kWaves];
-    float *halo = halo_all[threadIdx.x >> 6];
     FrameCounters &fcr = S.C->fc[seq & (kRing - 1)];
     const int64_t n = update_set_size(S.C, fcr);
     if (blockIdx.x == 0) {
@@ -563,7 +558,7 @@ __global__ void __launch_bounds__(kBlock) k_mc_extract(Dev S, int seq, int n_par
     for (int64_t t = gw; t < n; t += nw) {
         const int32_t pool = S.mclist[t];
         uint32_t out[8];
-        mc_block(S, pool, S.pool_key[pool], halo, out);
+        mc_block(S, pool, S.pool_key[pool], out);
 #pragma unroll
         for (int j = 0; j < 8; ++j) S.MCV[int64_t(pool) * 512 + lane + 64 * j] = out[j];
     }
@@ -572,8 +567,6 @@ __global__ void __launch_bounds__(kBlock) k_mc_extract(Dev S, int seq, int n_par
 // API form: keys -> uint8 index [n][512] and optional uint8 RGB [n][512][3].
 __global__ void __launch_bounds__(kBlock) k_mc_keys(Dev S, const int32_t *__restrict__ keys, int64_t n, uint8_t *mc,
                                                     uint8_t *rgb) {
-    __shared__ float halo_all[kWaves][kHalo];
-    float *halo = halo_all[threadIdx.x >> 6];
     const int lane = lane_id();
     const int64_t gw = int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6);
     const int64_t nw = int64_t(gridDim.x) * kWaves;
@@ -586,7 +579,7 @@ __global__ void __launch_bounds__(kBlock) k_mc_keys(Dev S, const int32_t *__rest
             if (ps >= 0) pool = S.T[ps].val;
         }
         uint32_t out[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (pool >= 0) mc_block(S, pool, pack_key(x, y, z), halo, out);
+        if (pool >= 0) mc_block(S, pool, pack_key(x, y, z), out);
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const int64_t o = t * 512 + lane + 64 * j;
@@ -682,14 +675,19 @@ __global__ void __launch_bounds__(kBlock) k_load_copy(Dev S, const int32_t *keys
     for (int64_t t = gw; t < n; t += nw) {
         const int32_t pool = lookup_pool(S, keys[3 * t], keys[3 * t + 1], keys[3 * t + 2]);
         if (pool < 0) continue;
+        uint32_t bits = 0;
         for (int j = 0; j < 8; ++j) {
             const int64_t i = t * 512 + lane + 64 * j;
             const int64_t o = int64_t(pool) * 512 + lane + 64 * j;
             uint32_t w = W[i];
             if (rgb) w |= uint32_t(rgb[3 * i]) << 8 | uint32_t(rgb[3 * i + 1]) << 16 | uint32_t(rgb[3 * i + 2]) << 24;
-            S.F[o] = F[i];
+            const float f = F[i];
+            S.F[o] = f;
             S.WRGB[o] = w;
+            const bool seen = (w & 0xFFu) && f == f;
+            bits |= uint32_t(seen && f < 0.0f) << j | uint32_t(seen) << (8 + j);
         }
+        S.SGN[int64_t(pool) * 64 + lane] = uint16_t(bits);
     }
 }
 
@@ -863,6 +861,7 @@ __global__ void __launch_bounds__(kBlock) k_reset_blocks(Dev S) {
         S.F[i] = 0.0f;
         S.WRGB[i] = 0u;
         S.MCV[i] = 0u;
+        if ((i & 511) < 64) S.SGN[(i >> 9) * 64 + (i & 511)] = 0;
         if ((i & 511) == 0) {
             S.pool_key[i >> 9] = 0;
             S.mc_stamp[i >> 9] = 0;
@@ -948,30 +947,38 @@ int scene_fuse(vbh_scene *s, const float *d_depth, const uint8_t *d_rgb, const f
                bool with_mc, hipStream_t st) {
     const Frame fr = make_frame(s, pose);
     const int seq = s->seq;
-    std::array<hipEvent_t, 5> ev{};
-    if (s->timing) {
+    // A timed update launches its kernels with start/stop events attached to the dispatch
+    // itself (no extra packets between the kernels).
+    StageTimer *tm = nullptr;
+    if (s->timing_period > 0 && seq % s->timing_period == 0) {
         if (s->ev_free.empty()) {
-            for (auto &e : ev) VBH_HIP(hipEventCreate(&e));
-        } else {
-            ev = s->ev_free.back();
-            s->ev_free.pop_back();
+            StageTimer t;
+            for (auto &e : t.ev) VBH_HIP(hipEventCreate(&e));
+            s->ev_free.push_back(t);
         }
-        s->ev_pending.push_back(ev);
+        s->ev_pending.push_back(s->ev_free.back());
+        s->ev_free.pop_back();
+        tm = &s->ev_pending.back();
+        tm->ran = 0;
     }
-    auto mark = [&](int i) { return s->timing ? hipEventRecord(ev[i], st) : hipSuccess; };
+    auto launch = [&](int stage, auto kern, dim3 grid, dim3 block, auto... args) {
+        if (tm) {
+            tm->ran |= 1u << stage;
+            hipExtLaunchKernelGGL(kern, grid, block, 0, st, tm->ev[2 * stage], tm->ev[2 * stage + 1], 0, args...);
+        } else {
+            hipLaunchKernelGGL(kern, grid, block, 0, st, args...);
+        }
+    };
     dim3 ga(unsigned((s->p.width + 31) / 32), unsigned((s->p.height + 8 * (kAllocThreads / 256) - 1) /
                                                         (8 * (kAllocThreads / 256))));
     const unsigned g = unsigned(s->cus) * 8;
     const unsigned gi = unsigned(s->cus) * 8;
-    VBH_HIP(mark(0));
-    k_alloc<<<ga, kAllocThreads, 0, st>>>(s->d, fr, d_depth, frame, seq);
-    VBH_HIP(mark(1));
-    k_integrate<<<gi, kBlock, 0, st>>>(s->d, fr, d_depth, d_rgb, seq);
-    VBH_HIP(mark(2));
-    if (with_mc) k_mc_mark<<<unsigned(s->cus) * 2, kMarkThreads, 0, st>>>(s->d, frame, seq);
-    VBH_HIP(mark(3));
-    if (with_mc) k_mc_extract<<<g / 2, kBlock, 0, st>>>(s->d, seq, int(gi));
-    VBH_HIP(mark(4));
+    launch(0, k_alloc, ga, dim3(kAllocThreads), s->d, fr, d_depth, frame, seq);
+    launch(1, k_integrate, dim3(gi), dim3(kBlock), s->d, fr, d_depth, d_rgb, seq);
+    if (with_mc) {
+        launch(2, k_mc_mark, dim3(unsigned(s->cus) * 2), dim3(kMarkThreads), s->d, frame, seq);
+        launch(3, k_mc_extract, dim3(g), dim3(kBlock), s->d, seq, int(gi));
+    }
     VBH_LAUNCHED();
     s->seq = seq + 1;
     s->last_frame = frame;
@@ -983,7 +990,7 @@ int scene_mc_update(vbh_scene *s, uint32_t frame, hipStream_t st) {
     if (seq < 0) return VBH_EINVAL;
     const unsigned g = unsigned(s->cus) * 8;
     k_mc_mark<<<unsigned(s->cus) * 2, kMarkThreads, 0, st>>>(s->d, frame, seq);
-    k_mc_extract<<<g / 2, kBlock, 0, st>>>(s->d, seq, int(g));
+    k_mc_extract<<<g, kBlock, 0, st>>>(s->d, seq, int(g));
     VBH_LAUNCHED();
     return VBH_OK;
 }
@@ -1019,8 +1026,8 @@ int vbh_scene_create(const vbh_params *p, vbh_scene **out) {
     const size_t sizes[] = {p->slots * sizeof(Slot), P * 512 * sizeof(float), P * 512 * 4, P * 512 * 4,
                             P * 8,                  P * 4,                     p->slots * 4, P * 4,
                             size_t(p->log_capacity) * 8, size_t(s->max_chunks) * 8, sizeof(Counters), 64 * 8,
-                            size_t(kMaxPartials) * 8};
-    for (int i = 0; i < 13; ++i) {
+                            size_t(kMaxPartials) * 8, P * 64 * 2};
+    for (int i = 0; i < 14; ++i) {
         if (hipMalloc(&s->mem[i], sizes[i]) != hipSuccess) {
             vbh_scene_destroy(s);
             return VBH_ENOMEM;
@@ -1045,8 +1052,10 @@ int vbh_scene_create(const vbh_params *p, vbh_scene **out) {
     d.C = s->C;
     s->hostbuf = static_cast<unsigned long long *>(s->mem[11]);
     d.partial = static_cast<unsigned long long *>(s->mem[12]);
+    d.SGN = static_cast<uint16_t *>(s->mem[13]);
     bool ok = vbh::table_init(d.T, p->slots, nullptr) == VBH_OK;
-    for (int i = 1; i <= 5 && ok; ++i) ok = hipMemset(s->mem[i], 0, sizes[i]) == hipSuccess;
+    for (int i : {1, 2, 3, 4, 5, 13})
+        if (ok) ok = hipMemset(s->mem[i], 0, sizes[i]) == hipSuccess;
     ok = ok && hipMemset(s->C, 0, sizeof(Counters)) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
     if (!ok) {
         vbh_scene_destroy(s);
@@ -1059,8 +1068,8 @@ int vbh_scene_create(const vbh_params *p, vbh_scene **out) {
 void vbh_scene_destroy(vbh_scene *s) {
     if (!s) return;
     for (auto *v : {&s->ev_pending, &s->ev_free})
-        for (auto &ev : *v)
-            for (auto e : ev) (void)hipEventDestroy(e);
+        for (auto &tm : *v)
+            for (auto e : tm.ev) (void)hipEventDestroy(e);
     for (void *m : s->mem)
         if (m) (void)hipFree(m);
     delete s;
@@ -1184,9 +1193,9 @@ int vbh_scene_log_entries(vbh_scene *s, uint64_t start, int64_t n, uint32_t *d_f
     return VBH_OK;
 }
 
-int vbh_scene_enable_timing(vbh_scene *s, int32_t enable) {
-    if (!s) return VBH_EINVAL;
-    s->timing = enable != 0;
+int vbh_scene_enable_timing(vbh_scene *s, int32_t period) {
+    if (!s || period < 0) return VBH_EINVAL;
+    s->timing_period = period;
     return VBH_OK;
 }
 
@@ -1194,13 +1203,13 @@ int vbh_scene_timing(vbh_scene *s, double *ms_out, int64_t *h_frames, void *stre
     if (!s || !ms_out) return VBH_EINVAL;
     VBH_HIP(hipStreamSynchronize(as_stream(stream)));
     for (int i = 0; i < 4; ++i) ms_out[i] = 0.0;
-    for (auto &ev : s->ev_pending) {
-        for (int i = 0; i < 4; ++i) {
+    for (auto &tm : s->ev_pending) {
+        for (int i = 0; i < kStages; ++i) {
             float ms = 0.0f;
-            VBH_HIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+            if (tm.ran >> i & 1u) VBH_HIP(hipEventElapsedTime(&ms, tm.ev[2 * i], tm.ev[2 * i + 1]));
             ms_out[i] += ms;
         }
-        s->ev_free.push_back(ev);
+        s->ev_free.push_back(tm);
     }
     if (h_frames) *h_frames = int64_t(s->ev_pending.size());
     s->ev_pending.clear();

@@ -20,6 +20,14 @@ constexpr int kWaves = kBlock / 64;
 constexpr int kChunk = 2048;  // log entries per workgroup chunk in the paged walk
 constexpr int kRing = 8;      // per-frame counter ring
 constexpr int kMaxPartials = 1 << 16;
+// Start/stop events of the fusion kernels of one timed update; bit i of `ran` is set if
+// stage i was launched.
+constexpr int kStages = 4;
+struct StageTimer {
+    std::array<hipEvent_t, 2 * kStages> ev{};
+    unsigned ran = 0;
+};
+
 // Same-address atomics serialise in L2 (about 10 ns each), so every kernel claims list
 // space and reports statistics once per workgroup, never once per wave.
 
@@ -52,6 +60,8 @@ struct Dev {
     float *F;            // [P][512]
     uint32_t *WRGB;      // [P][512] W | R<<8 | G<<16 | B<<24
     uint32_t *MCV;       // [P][512] index | R<<8 | G<<16 | B<<24
+    uint16_t *SGN;       // [P][64] per voxel column (x, y), index x + 8 y: bit z "F < 0 and
+                         // observed", bit 8 + z "observed" (W > 0, F not NaN); kept in step with F/W
     uint64_t *pool_key;  // [P]
     uint32_t *mc_stamp;  // [P]
     int32_t *touched;    // [slots] slot indices
@@ -92,9 +102,9 @@ struct vbh_scene {
     int seq = 0;        // number of updates so far (ring index of the next one)
     int cus = 256;      // compute units of the device the scene lives on
     uint32_t last_frame = 0;
-    void *mem[13] = {};
-    bool timing = false;
-    std::vector<std::array<hipEvent_t, 5>> ev_pending, ev_free;
+    void *mem[14] = {};
+    int timing_period = 0;  // time the kernels of every n-th update (0: off)
+    std::vector<vbh::StageTimer> ev_pending, ev_free;
 };
 
 

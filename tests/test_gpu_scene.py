@@ -196,3 +196,37 @@ def test_scene_errors(orc):
     G3 = vbh.Scene(vbh.make_params(tiny_log, configs.TINY_CAM))
     G3.vbh_integrate_frame(to_dev(depth[0].numpy()), None, poses[0], 1)
     assert G3.vbh_scene_status() == vbh.binding.VBH_EFULL_LOG
+
+
+def test_ragged_empty_and_invalid_frames(orc):
+    """A 101x77 camera (no dimension a multiple of the 32x16 allocation tile or the 8x8
+    wave tile), an all-zero frame, a frame whose depths all lie outside [dmin, dmax], and a
+    frame fused on top of blocks written through the ABI: touched/new/MC sets, state and MC
+    voxels against the oracle after every frame."""
+    vbh = require_gpu()
+    cam = configs.Camera(101, 77, 90.0, 90.0, 50.0, 38.0)
+    vol = configs.Volume(**{**configs.TINY_VOL.__dict__, "depth_min": 0.3, "depth_max": 3.0})
+    _, depth, rgb, poses = configs.tiny_inputs(6, cam=cam)
+    depth, rgb = depth.numpy().copy(), rgb.numpy().copy()
+    depth[2] = 0.0                                   # every pixel invalid
+    depth[3] = np.where(depth[3] > 0, 3.5, 0.0)      # every depth beyond dmax
+    G, O = make_pair(vbh, orc, vol, cam)
+    integrate_both(G, O, depth, rgb, poses, range(2))
+    for f in (2, 3):
+        integrate_both(G, O, depth, rgb, poses, [f], first_id=f + 1)
+        st = G.vbh_scene_stats()
+        assert st["n_touched"] == 0 and st["n_new"] == 0 and st["n_mc"] == 0
+    # overwrite some blocks (sign words rebuilt from the written voxels), then fuse on top
+    keys, _ = sort_keys(O.blocks())
+    sel = keys[::3]
+    rng = np.random.default_rng(7)
+    F = rng.normal(0.0, 0.02, (sel.shape[0], 512)).astype(np.float32)
+    W = np.where(rng.random(F.shape) < 0.2, 0, rng.integers(1, 200, size=F.shape)).astype(np.uint8)
+    c = rng.integers(0, 256, size=F.shape + (3,)).astype(np.uint8)
+    G.vbh_scene_write_blocks(to_dev(sel), to_dev(F), to_dev(W), to_dev(c), 5)
+    assert O.write(sel, F, W, c, 5) == 0
+    integrate_both(G, O, depth, rgb, poses, [4, 5], first_id=6)
+    k2, F2, W2, rgb2, gmc, grgb = compare_state(G, O)
+    mc_on_identical_input(orc, vol, cam, k2, F2, W2, rgb2, gmc, grgb)
+    emc, ergb = G.vbh_extract_mc_indices(to_dev(k2))
+    assert np.array_equal(emc.cpu().numpy(), gmc) and np.array_equal(ergb.cpu().numpy(), grgb)
