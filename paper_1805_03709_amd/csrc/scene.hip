@@ -22,10 +22,8 @@ namespace {
 
 
 // Blocks in the MC update set of the update whose counters are fc (valid once its
-// marking has finished): the length of its log segment.
-__device__ __forceinline__ int64_t update_set_size(const Counters *C, const FrameCounters &fc) {
-    return int64_t(C->log_len - fc.log_base);
-}
+// marking has finished).
+__device__ __forceinline__ int64_t update_set_size(const FrameCounters &fc) { return int64_t(fc.n_mc); }
 
 // Starts update `seq`: clears the counters two updates ahead in the ring and records
 // where this update's log segment begins.  Called by exactly one thread.
@@ -62,6 +60,46 @@ __device__ __forceinline__ void stage_put(StageBuf<CAP> &b, bool put, int32_t v)
     if (put) b.item[pos + unsigned(lanes_below(m))] = v;
 }
 
+// ---------------------------------------------------------------- MC update set
+// Block B - e of a touched block B, e in {0,1}^3, joins the frame's MC update set (the
+// touched blocks and their seven negative neighbours, Sec. 4.2) if it exists.  The first
+// thread to raise its MC stamp appends it to the update's MC list; the extraction kernel
+// later copies the list into the update log.
+__device__ __forceinline__ bool try_mark(const Dev &S, int32_t target, uint32_t frame) {
+    return target >= 0 && atomicMax(&S.mc_stamp[target], frame) < frame;
+}
+
+// Pool index of the block B - e (e in {0,1}^3 \ {0}) if it exists and its pool block is
+// published, else -1.
+__device__ __forceinline__ int32_t negative_neighbour(const Dev &S, int32_t bx, int32_t by, int32_t bz, int e) {
+    const int32_t nx = bx - (e & 1), ny = by - ((e >> 1) & 1), nz = bz - ((e >> 2) & 1);
+    if (!key_ok(nx, ny, nz)) return -1;
+    const uint64_t nk = pack_key(nx, ny, nz);
+    // the slot's key and value are read together at every probe step
+    uint64_t p = home_slot(nx, ny, nz, nk, S.kind, S.mask);
+    for (uint64_t n = 0; n <= S.mask; ++n) {
+        const uint64_t k = ld_key(S.T + p);
+        const int32_t v = __hip_atomic_load(&S.T[p].val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (k == nk) return v >= 0 ? v : -1;
+        if (k == kEmpty) return -1;
+        p = (p + 1) & S.mask;
+    }
+    return -1;
+}
+
+// Appends the workgroup's staged MC-set blocks to the update's MC list (one atomic) and
+// empties the buffer.  Called by every thread of the workgroup.
+template <int CAP>
+__device__ __forceinline__ void flush_mc(const Dev &S, FrameCounters *fc, StageBuf<CAP> &b) {
+    __syncthreads();
+    if (threadIdx.x == 0) b.base = b.count ? atomicAdd(&fc->n_mc, b.count) : 0u;
+    __syncthreads();
+    for (unsigned int k = threadIdx.x; k < b.count; k += blockDim.x) S.mclist[b.base + k] = b.item[k];
+    __syncthreads();
+    if (threadIdx.x == 0) b.count = 0;
+    __syncthreads();
+}
+
 // ------------------------------------------------------------------ allocation
 // One workgroup per 32x16-pixel tile, thread = pixel.  Each valid pixel takes 2m+1 band
 // samples at camera depth lam = (d - mu) + s*vs:
@@ -75,20 +113,32 @@ __device__ __forceinline__ void stage_put(StageBuf<CAP> &b, bool put, int32_t v)
 // keys are claimed with a CAS (and get pool blocks from one reservation per workgroup),
 // and the thread that raises a block's frame stamp appends it to the touched list (one
 // atomic per workgroup, shared with the new-block count).
+//
+// With `mark`, the kernel also forms the update's MC set.  Blocks that existed before the
+// frame are found by any probe (keys never move); a block allocated by this frame is
+// touched, so it enters the set as a touched block whether or not a neighbour's probe
+// saw it.  Hence: the appending thread of a touched block B marks B's existing negative
+// neighbours and, if B's pool block is already known, B itself; the claiming thread of a
+// new block marks it once its pool block is assigned.
 constexpr int kAllocThreads = 512;  // 32x16 pixels: eight 8x8 wave tiles
 constexpr int kSetSlots = 2048;     // LDS hash set of keys (load <= 1/2, see kListFlush)
 constexpr int kListCap = 1024;      // distinct keys collected before they are processed
 constexpr int kListFlush = kListCap - kAllocThreads;  // one sample step adds <= 512 keys
+constexpr int kMcCap = 2048;        // staged MC-set blocks (<= 1024 from claims, then
+                                    // flushed above kMcCap - 512 after each marking round)
 
 __device__ __forceinline__ uint32_t set_hash(uint64_t k) {
     return uint32_t((k * 0x9E3779B97F4A7C15ull) >> 40);
 }
 
 __global__ void __launch_bounds__(kAllocThreads) k_alloc(Dev S, Frame fr, const float *__restrict__ depth,
-                                                         uint32_t frame, int seq) {
+                                                         uint32_t frame, int seq, int mark) {
     __shared__ unsigned long long set[kSetSlots];
     __shared__ unsigned long long list[kListCap];
     __shared__ int32_t appended[kListCap];
+    __shared__ uint16_t app_idx[kListCap];  // list index of each appended block
+    __shared__ int32_t app_pool[kListCap];  // its pool block if it still has to be marked, else -1
+    __shared__ StageBuf<kMcCap> mcb;
     __shared__ unsigned int n_list, n_app, n_claim, n_new_wg;
     __shared__ unsigned long long pool_base;
     FrameCounters *fc = &S.C->fc[seq & (kRing - 1)];
@@ -99,6 +149,7 @@ __global__ void __launch_bounds__(kAllocThreads) k_alloc(Dev S, Frame fr, const 
         n_app = 0;
         n_claim = 0;
         n_new_wg = 0;
+        mcb.count = 0;
     }
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
@@ -164,11 +215,12 @@ __global__ void __launch_bounds__(kAllocThreads) k_alloc(Dev S, Frame fr, const 
         }
         __syncthreads();
         const unsigned int nl = n_list;
+        __syncthreads();  // every thread has read n_list before it changes again
         if (nl <= unsigned(kListFlush) && s + 1 < n_samples) continue;  // uniform
         // the collected distinct keys against the global table, one thread per key
         for (unsigned int r = 0; r < nl; r += kAllocThreads) {  // uniform
             const unsigned int i = r + threadIdx.x;
-            int32_t slot = -1;
+            int32_t slot = -1, pool = -1;  // pool: the block's pool index if known, else -1
             bool claimed = false, stamp_now = false;
             uint64_t key = kEmpty;
             unsigned int cidx = 0;
@@ -178,36 +230,45 @@ __global__ void __launch_bounds__(kAllocThreads) k_alloc(Dev S, Frame fr, const 
                 unpack_key(key, x, y, z);
                 const uint32_t home = uint32_t(home_slot(x, y, z, key, S.kind, S.mask));
                 const uint64_t first = ld_key(S.T + home);
+                const int32_t hv = __hip_atomic_load(&S.T[home].val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 const uint32_t st = __hip_atomic_load(&S.T[home].stamp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (first == key) {
                     slot = int32_t(home);
                     stamp_now = st == frame;  // already touched by this frame
+                    pool = hv >= 0 ? hv : -1;
                 } else {
                     slot = int32_t(probe_claim(S.T, S.mask, key, home, claimed));
-                    if (slot < 0) raise_err(&S.C->err, kErrTableFull);
+                    if (slot < 0) {
+                        raise_err(&S.C->err, kErrTableFull);
+                    } else if (!claimed && mark) {
+                        const int32_t v = __hip_atomic_load(&S.T[slot].val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        pool = v >= 0 ? v : -1;
+                    }
                 }
                 if (claimed) cidx = atomicAdd(&n_claim, 1u);
             }
             __syncthreads();
             const unsigned int nc = n_claim;
+            __syncthreads();  // every thread has read n_claim before it is reset
             if (nc) {  // uniform: one pool reservation per workgroup and round
                 if (threadIdx.x == 0) {
                     pool_base = atomicAdd(&S.C->pool_next, (unsigned long long)nc);
                     n_new_wg += nc;
+                    n_claim = 0;
                 }
                 __syncthreads();
                 if (claimed) {
-                    const unsigned long long pool = pool_base + cidx;
-                    if (int64_t(pool) < S.pool_cap) {
-                        S.pool_key[pool] = key;
-                        st_val(S.T + slot, int32_t(pool));
+                    const unsigned long long pb = pool_base + cidx;
+                    if (int64_t(pb) < S.pool_cap) {
+                        S.pool_key[pb] = key;
+                        st_val(S.T + slot, int32_t(pb));
+                        pool = int32_t(pb);
                     } else {
                         st_val(S.T + slot, kNoPool);
                         raise_err(&S.C->err, kErrPoolFull);
                     }
                 }
-                if (threadIdx.x == 0) n_claim = 0;  // every thread read it before the barrier above
-                __syncthreads();
+                if (mark) stage_put(mcb, claimed && try_mark(S, pool, frame), pool);  // new block: its claimer marks it
             }
             const bool app = slot >= 0 && !stamp_now && atomicMax(&S.T[slot].stamp, frame) < frame;
             const unsigned long long m = __ballot(app);
@@ -216,7 +277,12 @@ __global__ void __launch_bounds__(kAllocThreads) k_alloc(Dev S, Frame fr, const 
                 unsigned int p0 = 0;
                 if (lane == leader) p0 = atomicAdd(&n_app, unsigned(__popcll(m)));
                 p0 = __shfl(p0, leader);
-                if (app) appended[p0 + unsigned(lanes_below(m))] = slot;
+                if (app) {
+                    const unsigned int q = p0 + unsigned(lanes_below(m));
+                    appended[q] = slot;
+                    app_idx[q] = uint16_t(i);
+                    app_pool[q] = claimed ? -1 : pool;
+                }
             }
         }
         __syncthreads();
@@ -230,6 +296,30 @@ __global__ void __launch_bounds__(kAllocThreads) k_alloc(Dev S, Frame fr, const 
         }
         __syncthreads();
         for (unsigned int i = threadIdx.x; i < n_app; i += kAllocThreads) S.touched[pool_base + i] = appended[i];
+        if (mark) {  // uniform: MC-set marking, thread per (appended block, e in {0,1}^3)
+            const unsigned int items = n_app * 8u;
+            for (unsigned int r = 0; r < items; r += kAllocThreads) {
+                const unsigned int it = r + threadIdx.x;
+                int32_t target = -1;
+                if (it < items) {
+                    const unsigned int b = it >> 3, e = it & 7u;
+                    if (e == 0) {
+                        target = app_pool[b];
+                    } else {
+                        int32_t x, y, z;
+                        unpack_key(list[app_idx[b]], x, y, z);
+                        target = negative_neighbour(S, x, y, z, int(e));
+                    }
+                }
+                stage_put(mcb, try_mark(S, target, frame), target);
+                __syncthreads();
+                const unsigned int c = mcb.count;
+                __syncthreads();  // every thread has read the count before it changes again
+                if (c > unsigned(kMcCap - kAllocThreads)) flush_mc(S, fc, mcb);
+            }
+            __syncthreads();
+            if (mcb.count) flush_mc(S, fc, mcb);  // no thread stages again before this flush
+        }
         if (s + 1 < n_samples) {  // start a new collection
             for (int i = threadIdx.x; i < kSetSlots; i += kAllocThreads) set[i] = kEmpty;
             prev = kEmpty;
@@ -241,26 +331,6 @@ __global__ void __launch_bounds__(kAllocThreads) k_alloc(Dev S, Frame fr, const 
         }
         __syncthreads();
     }
-}
-
-// ---------------------------------------------------------------- MC update set
-// Thread per (touched block, e in {0,1}^3): block B - e, if it exists, joins the frame's
-// MC update set (the touched blocks and their seven negative neighbours).  The first
-// thread to raise its MC stamp appends it to the MC list and to the update log.
-__device__ __forceinline__ bool try_mark(const Dev &S, int32_t target, uint32_t frame) {
-    if (target < 0) return false;
-    const uint32_t cur = __hip_atomic_load(&S.mc_stamp[target], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return cur != frame && atomicMax(&S.mc_stamp[target], frame) < frame;
-}
-
-// Appends a marked block at log position lpos (the MC list is the update's log segment).
-__device__ __forceinline__ void put_log(const Dev &S, const FrameCounters &fc, unsigned long long lpos, int32_t target,
-                                        uint32_t frame) {
-    S.mclist[lpos - fc.log_base] = target;
-    if (lpos < S.log_cap)
-        S.log[lpos] = (uint64_t(frame) << 32) | uint32_t(target);
-    else
-        raise_err(&S.C->err, kErrLogFull);
 }
 
 __device__ __forceinline__ uint64_t first_lane64(uint64_t v) {
@@ -405,10 +475,9 @@ __global__ void __launch_bounds__(kBlock) k_integrate(Dev S, Frame fr, const flo
     if (threadIdx.x == 0) S.partial[blockIdx.x] = wg_updates;
 }
 
-// Thread per (touched block, e in {0,1}^3): block B - e, if it exists, joins the
-// update's MC set (the touched blocks and their seven negative neighbours).  The first
-// thread to raise its MC stamp appends it; appends are staged per workgroup in LDS and
-// claimed in the log with one atomic per workgroup.
+// Stand-alone MC-set marking for updates fused without it (the serving loop fuses a
+// frame first and runs its MC update later): thread per (touched block, e in {0,1}^3),
+// appends staged per workgroup in LDS and claimed with one atomic per flush.
 constexpr int kMarkThreads = 1024;
 __global__ void __launch_bounds__(kMarkThreads) k_mc_mark(Dev S, uint32_t frame, int seq) {
     constexpr int kCap = 4 * kMarkThreads;
@@ -430,26 +499,15 @@ __global__ void __launch_bounds__(kMarkThreads) k_mc_mark(Dev S, uint32_t frame,
                 } else {
                     int32_t bx, by, bz;
                     unpack_key(sl->key, bx, by, bz);
-                    const int32_t nx = bx - (e & 1), ny = by - ((e >> 1) & 1), nz = bz - ((e >> 2) & 1);
-                    if (key_ok(nx, ny, nz)) {
-                        const uint64_t nk = pack_key(nx, ny, nz);
-                        const int64_t ps = probe_locate(S.T, S.mask, nk, home_slot(nx, ny, nz, nk, S.kind, S.mask));
-                        if (ps >= 0) target = S.T[ps].val;
-                    }
+                    target = negative_neighbour(S, bx, by, bz, e);
                 }
             }
         }
         stage_put(mb, try_mark(S, target, frame), target);
         __syncthreads();
-        if (mb.count > unsigned(kCap - kMarkThreads) || b0 + stride >= total) {
-            if (threadIdx.x == 0) mb.base = mb.count ? atomicAdd(&S.C->log_len, (unsigned long long)mb.count) : 0;
-            __syncthreads();
-            for (unsigned int k = threadIdx.x; k < mb.count; k += kMarkThreads)
-                put_log(S, *fc, mb.base + k, mb.item[k], frame);
-            __syncthreads();
-            if (threadIdx.x == 0) mb.count = 0;
-            __syncthreads();
-        }
+        const unsigned int c = mb.count;
+        __syncthreads();  // every thread has read the count before it changes again
+        if (c > unsigned(kCap - kMarkThreads) || b0 + stride >= total) flush_mc(S, fc, mb);
     }
 }
 
@@ -530,13 +588,15 @@ __device__ __forceinline__ void mc_block(const Dev &S, int32_t pool, uint64_t ke
         out[j] = (keep >> j) & 1u ? (uint32_t(idx >> (8 * j)) & 0xFFu) | (colour[j] & 0xFFFFFF00u) : 0u;
 }
 
-// Per-frame form: MC list -> MC pool.
+// Per-frame form: MC list -> MC pool, and the MC list appended to the update log as
+// entries (frame << 32 | pool) at [log_base, log_base + n).
 // Workgroup 0 also folds the integration kernel's n_partials per-workgroup voxel counts
-// into the update's statistics.
-__global__ void __launch_bounds__(kBlock) k_mc_extract(Dev S, int seq, int n_partials) {
+// into the update's statistics and advances the log length.
+__global__ void __launch_bounds__(kBlock) k_mc_extract(Dev S, int seq, int n_partials, uint32_t frame) {
     __shared__ unsigned long long red[kWaves];
     FrameCounters &fcr = S.C->fc[seq & (kRing - 1)];
-    const int64_t n = update_set_size(S.C, fcr);
+    const int64_t n = update_set_size(fcr);
+    const unsigned long long log_base = fcr.log_base;
     if (blockIdx.x == 0) {
         unsigned long long v = 0;
         for (int i = threadIdx.x; i < n_partials; i += kBlock) v += S.partial[i];
@@ -547,6 +607,8 @@ __global__ void __launch_bounds__(kBlock) k_mc_extract(Dev S, int seq, int n_par
             unsigned long long tot = 0;
             for (int w = 0; w < kWaves; ++w) tot += red[w];
             fcr.voxel_updates = tot;
+            S.C->log_len = log_base + (unsigned long long)n;
+            if (log_base + (unsigned long long)n > S.log_cap) raise_err(&S.C->err, kErrLogFull);
             S.C->tot_mc += n;
             S.C->tot_touched += fcr.n_touched;
             S.C->tot_voxel_updates += tot;
@@ -557,6 +619,7 @@ __global__ void __launch_bounds__(kBlock) k_mc_extract(Dev S, int seq, int n_par
     const int64_t nw = int64_t(gridDim.x) * kWaves;
     for (int64_t t = gw; t < n; t += nw) {
         const int32_t pool = S.mclist[t];
+        if (lane_id() == 0 && log_base + t < S.log_cap) S.log[log_base + t] = (uint64_t(frame) << 32) | uint32_t(pool);
         uint32_t out[8];
         mc_block(S, pool, S.pool_key[pool], out);
 #pragma unroll
@@ -699,7 +762,7 @@ __global__ void __launch_bounds__(kBlock) k_keys_of(Dev S, int which, int seq, i
         n = int64_t(pn) < S.pool_cap ? int64_t(pn) : S.pool_cap;
     } else {
         const FrameCounters &fc = S.C->fc[seq & (kRing - 1)];
-        n = which == 1 ? int64_t(fc.n_touched) : update_set_size(S.C, fc);
+        n = which == 1 ? int64_t(fc.n_touched) : update_set_size(fc);
     }
     if (n > cap) n = cap;
     for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock) {
@@ -829,7 +892,7 @@ __global__ void k_read_counters(const Counters *C, int seq, unsigned long long *
     out[9] = C->tot_voxel_updates;
     out[0] = fc.n_touched;
     out[1] = fc.n_new;
-    out[2] = C->log_len - fc.log_base;
+    out[2] = fc.n_mc;
     out[3] = fc.voxel_updates;
     out[4] = C->pool_next;
     out[5] = C->log_len;
@@ -889,7 +952,7 @@ unsigned wave_grid(const vbh_scene *s, int64_t cap_items) {
 int mc_update(vbh_scene *s, uint32_t frame, int seq, hipStream_t st) {
     const unsigned g = unsigned(s->cus) * 8;
     k_mc_mark<<<unsigned(s->cus) * 2, kMarkThreads, 0, st>>>(s->d, frame, seq);
-    k_mc_extract<<<g, kBlock, 0, st>>>(s->d, seq, 0);
+    k_mc_extract<<<g, kBlock, 0, st>>>(s->d, seq, 0, frame);
     VBH_LAUNCHED();
     return VBH_OK;
 }
@@ -973,12 +1036,9 @@ int scene_fuse(vbh_scene *s, const float *d_depth, const uint8_t *d_rgb, const f
                                                         (8 * (kAllocThreads / 256))));
     const unsigned g = unsigned(s->cus) * 8;
     const unsigned gi = unsigned(s->cus) * 8;
-    launch(0, k_alloc, ga, dim3(kAllocThreads), s->d, fr, d_depth, frame, seq);
+    launch(0, k_alloc, ga, dim3(kAllocThreads), s->d, fr, d_depth, frame, seq, int(with_mc));  // marks the MC set
     launch(1, k_integrate, dim3(gi), dim3(kBlock), s->d, fr, d_depth, d_rgb, seq);
-    if (with_mc) {
-        launch(2, k_mc_mark, dim3(unsigned(s->cus) * 2), dim3(kMarkThreads), s->d, frame, seq);
-        launch(3, k_mc_extract, dim3(g), dim3(kBlock), s->d, seq, int(gi));
-    }
+    if (with_mc) launch(3, k_mc_extract, dim3(g), dim3(kBlock), s->d, seq, int(gi), frame);
     VBH_LAUNCHED();
     s->seq = seq + 1;
     s->last_frame = frame;
@@ -990,7 +1050,7 @@ int scene_mc_update(vbh_scene *s, uint32_t frame, hipStream_t st) {
     if (seq < 0) return VBH_EINVAL;
     const unsigned g = unsigned(s->cus) * 8;
     k_mc_mark<<<unsigned(s->cus) * 2, kMarkThreads, 0, st>>>(s->d, frame, seq);
-    k_mc_extract<<<g, kBlock, 0, st>>>(s->d, seq, int(g));
+    k_mc_extract<<<g, kBlock, 0, st>>>(s->d, seq, int(g), frame);
     VBH_LAUNCHED();
     return VBH_OK;
 }

@@ -34,11 +34,11 @@ struct StageTimer {
 struct FrameCounters {
     unsigned int n_touched;
     unsigned int n_new;
-    unsigned int pad0;
-    unsigned int pad1;
+    unsigned int n_mc;  // blocks in the update's MC set (entries of the MC list)
+    unsigned int pad;
     unsigned long long voxel_updates;
-    unsigned long long log_base;  // log length when the update started; the update's MC
-                                  // list is its log segment [log_base, log_len)
+    unsigned long long log_base;  // log length when the update started; the extraction
+                                  // kernel writes the MC list to [log_base, log_base + n_mc)
 };
 
 struct Counters {
@@ -65,7 +65,7 @@ struct Dev {
     uint64_t *pool_key;  // [P]
     uint32_t *mc_stamp;  // [P]
     int32_t *touched;    // [slots] slot indices
-    int32_t *mclist;     // [P] pool indices
+    int32_t *mclist;     // [P] pool indices of the current update's MC set
     uint64_t *log;       // [L] (frame << 32) | pool
     int64_t *prefix;     // [max_chunks + 1] scratch of the paged walk
     unsigned long long *partial;  // [kMaxPartials] per-workgroup statistics, reduced later
