@@ -160,6 +160,15 @@ void vbh_scene_destroy(vbh_scene *s);
 int vbh_integrate_frame(vbh_scene *s, const float *d_depth, const uint8_t *d_rgb, const float *pose_c2w,
                         uint32_t frame_id, void *stream);
 
+/* Fuse n consecutive frames, each exactly as vbh_integrate_frame would, in order: d_depth
+ * float32 [n][H*W], d_rgb uint8 [n][H*W*3] or NULL, poses_c2w a HOST array of n*12 floats
+ * (copied), frame ids first_frame_id .. first_frame_id + n - 1 (first_frame_id > 0 and
+ * greater than every previous frame id, else VBH_EINVAL; n = 0 does nothing).  Every
+ * result equals that of n vbh_integrate_frame calls; the call returns once the last
+ * frame is enqueued, keeping at most 64 frames queued ahead of the device. */
+int vbh_integrate_frames(vbh_scene *s, const float *d_depth, const uint8_t *d_rgb, const float *poses_c2w,
+                         uint32_t first_frame_id, int64_t n, void *stream);
+
 /* MC voxels (Sec. 4.2) recomputed from the current TSDF for n blocks: d_mc uint8
  * [n*512] case indices (bit k set iff corner k, Lorensen-Cline order (0,0,0) (1,0,0)
  * (1,1,0) (0,1,0) (0,0,1) (1,0,1) (1,1,1) (0,1,1), has F < 0; 0 if any corner lies in a
@@ -204,10 +213,11 @@ int vbh_scene_write_blocks(vbh_scene *s, const int32_t *d_keys, int64_t n, const
  * B has a frame <= V. */
 int vbh_scene_log_entries(vbh_scene *s, uint64_t start, int64_t n, uint32_t *d_frame, int32_t *d_keys, void *stream);
 
-/* Stage timing.  With period n > 0, every n-th update of vbh_integrate_frame launches its
- * kernels (band allocation, integration, MC update-set marking, MC extraction) with HIP
+/* Stage timing.  With period n > 0, every n-th update launches its kernels with HIP
  * start/stop events attached to the kernel dispatches on the caller's stream; period 0
- * turns timing off (the default).  vbh_scene_timing synchronises the stream and returns,
+ * turns timing off (the default).  Stages: 0 band allocation with MC-set marking,
+ * 1 integration, 2 stand-alone MC-set marking (not used by frame fusion, whose allocation
+ * kernel forms the MC set), 3 MC extraction.  vbh_scene_timing synchronises the stream and returns,
  * per stage, the summed kernel milliseconds and the number of updates measured since the
  * last call (then resets).  ms_out must hold VBH_N_STAGES doubles.  EINVAL for period < 0. */
 #define VBH_N_STAGES 4

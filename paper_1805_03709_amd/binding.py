@@ -11,6 +11,8 @@ from __future__ import annotations
 import ctypes as C
 import os
 
+import numpy as np
+
 import torch
 
 from .build import LIB
@@ -88,6 +90,7 @@ SIGNATURES = {
     "vbh_scene_create": ([C.POINTER(vbh_params), C.POINTER(_V)], C.c_int),
     "vbh_scene_destroy": ([_V], None),
     "vbh_integrate_frame": ([_V, _P, _P, C.POINTER(C.c_float), C.c_uint32, _V], C.c_int),
+    "vbh_integrate_frames": ([_V, _P, _P, C.POINTER(C.c_float), C.c_uint32, _I64, _V], C.c_int),
     "vbh_extract_mc_indices": ([_V, _P, _I64, _P, _P, _V], C.c_int),
     "vbh_stored_mc": ([_V, _P, _I64, _P, _P, _V], C.c_int),
     "vbh_updated_blocks_since": ([_V, _U64, _I64, _P, _P, _P, _V], C.c_int),
@@ -159,6 +162,15 @@ def _ptr(t, dtype=None, n=None, name="tensor"):
     if n is not None and t.numel() < n:
         raise ValueError(f"{name} has {t.numel()} elements, needs {n}")
     return C.c_void_p(t.data_ptr())
+
+
+def _poses_f32(poses, n):
+    """n camera-to-world poses ([n][3][4] or [n][12], any float type, host or device) as a
+    contiguous float32 [n][12] host array (each value rounded to nearest)."""
+    if isinstance(poses, torch.Tensor):
+        poses = poses.detach().cpu().numpy()
+    a = np.asarray(poses, dtype=np.float64).reshape(n, -1)[:, :12]
+    return np.ascontiguousarray(a, dtype=np.float32)
 
 
 def _keys(keys):
@@ -257,10 +269,22 @@ class Scene:
     def vbh_integrate_frame(self, depth, rgb, pose_c2w, frame_id: int):
         p = self.params
         n = p.width * p.height
-        pose = (C.c_float * 12)(*[float(x) for x in torch.as_tensor(pose_c2w, dtype=torch.float64).reshape(-1)[:12]])
+        P = _poses_f32(pose_c2w, 1)
+        pose = P.ctypes.data_as(C.POINTER(C.c_float))
         _check(lib().vbh_integrate_frame(self.h, _ptr(depth, torch.float32, n, "depth"),
                                          _ptr(rgb, torch.uint8, 3 * n, "rgb"), pose, frame_id, _stream()),
                "vbh_integrate_frame")
+
+    def vbh_integrate_frames(self, depth, rgb, poses_c2w, first_frame_id: int):
+        """Fuse frames depth[i] (rgb[i], poses_c2w[i]) as ids first_frame_id + i."""
+        p = self.params
+        n = int(depth.shape[0]) if depth is not None else 0
+        hw = p.width * p.height
+        P = _poses_f32(poses_c2w, n) if n > 0 else np.zeros((1, 12), np.float32)
+        poses = P.ctypes.data_as(C.POINTER(C.c_float))
+        _check(lib().vbh_integrate_frames(self.h, _ptr(depth, torch.float32, n * hw, "depth"),
+                                          _ptr(rgb, torch.uint8, 3 * n * hw, "rgb"), poses, first_frame_id, n,
+                                          _stream()), "vbh_integrate_frames")
 
     def vbh_extract_mc_indices(self, keys, with_rgb=True):
         kp, n = _keys(keys)
@@ -388,9 +412,7 @@ class Server:
         for i, (d, c, pose, t, fid) in enumerate(frames):
             feed[i].d_depth = _ptr(d, torch.float32)
             feed[i].d_rgb = _ptr(c, torch.uint8) if c is not None else None
-            P = torch.as_tensor(pose, dtype=torch.float64).reshape(-1)[:12]
-            for j in range(12):
-                feed[i].pose_c2w[j] = float(P[j])
+            feed[i].pose_c2w[:] = _poses_f32(pose, 1).reshape(-1).tolist()
             feed[i].time_s, feed[i].frame_id = float(t), int(fid)
         res = (vbh_request_result * max(n, 1))()
         torch.cuda.synchronize()

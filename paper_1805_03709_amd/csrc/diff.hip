@@ -79,7 +79,7 @@ __global__ void __launch_bounds__(kBlock) k_zero_grad_blocks(DiffDev D) {
 __global__ void __launch_bounds__(kBlock) k_touch_mask(DiffDev D, int f, int seq) {
     const int64_t n = D.S.C->fc[seq & (kRing - 1)].n_touched;
     for (int64_t t = int64_t(blockIdx.x) * kBlock + threadIdx.x; t < n; t += int64_t(gridDim.x) * kBlock) {
-        const int32_t pool = D.S.T[D.S.touched[t]].val;
+        const int32_t pool = D.S.T[touched_of(D.S, seq)[t]].val;
         if (pool >= 0) D.fmask[pool] |= 1u << f;  // each block appears once per update
     }
 }

@@ -26,11 +26,14 @@ namespace {
 __device__ __forceinline__ int64_t update_set_size(const FrameCounters &fc) { return int64_t(fc.n_mc); }
 
 // Starts update `seq`: clears the counters two updates ahead in the ring and records
-// where this update's log segment begins.  Called by exactly one thread.
+// where this update's log segment begins: after the previous update's segment, whose size
+// is final once that update's allocation (or marking) kernel has finished, even while its
+// extraction kernel, which writes the segment, still runs.  Called by exactly one thread.
 __device__ __forceinline__ void begin_update(const Dev &S, int seq) {
     FrameCounters z = {};
     S.C->fc[(seq + 2) & (kRing - 1)] = z;
-    S.C->fc[seq & (kRing - 1)].log_base = S.C->log_len;
+    const FrameCounters &prev = S.C->fc[(seq - 1) & (kRing - 1)];
+    S.C->fc[seq & (kRing - 1)].log_base = seq > 0 ? prev.log_base + prev.n_mc : S.C->log_len;
 }
 
 // Workgroup staging buffer for list appends: waves reserve space with one LDS atomic,
@@ -90,11 +93,11 @@ __device__ __forceinline__ int32_t negative_neighbour(const Dev &S, int32_t bx, 
 // Appends the workgroup's staged MC-set blocks to the update's MC list (one atomic) and
 // empties the buffer.  Called by every thread of the workgroup.
 template <int CAP>
-__device__ __forceinline__ void flush_mc(const Dev &S, FrameCounters *fc, StageBuf<CAP> &b) {
+__device__ __forceinline__ void flush_mc(int32_t *mclist, FrameCounters *fc, StageBuf<CAP> &b) {
     __syncthreads();
     if (threadIdx.x == 0) b.base = b.count ? atomicAdd(&fc->n_mc, b.count) : 0u;
     __syncthreads();
-    for (unsigned int k = threadIdx.x; k < b.count; k += blockDim.x) S.mclist[b.base + k] = b.item[k];
+    for (unsigned int k = threadIdx.x; k < b.count; k += blockDim.x) mclist[b.base + k] = b.item[k];
     __syncthreads();
     if (threadIdx.x == 0) b.count = 0;
     __syncthreads();
@@ -120,6 +123,7 @@ __device__ __forceinline__ void flush_mc(const Dev &S, FrameCounters *fc, StageB
 // saw it.  Hence: the appending thread of a touched block B marks B's existing negative
 // neighbours and, if B's pool block is already known, B itself; the claiming thread of a
 // new block marks it once its pool block is assigned.
+//
 constexpr int kAllocThreads = 512;  // 32x16 pixels: eight 8x8 wave tiles
 constexpr int kSetSlots = 2048;     // LDS hash set of keys (load <= 1/2, see kListFlush)
 constexpr int kListCap = 1024;      // distinct keys collected before they are processed
@@ -127,22 +131,36 @@ constexpr int kListFlush = kListCap - kAllocThreads;  // one sample step adds <=
 constexpr int kMcCap = 2048;        // staged MC-set blocks (<= 1024 from claims, then
                                     // flushed above kMcCap - 512 after each marking round)
 
+// Workgroup-shared state of the allocation.
+struct AllocShared {
+    unsigned long long set[kSetSlots];
+    unsigned long long list[kListCap];
+    int32_t appended[kListCap];
+    uint16_t app_idx[kListCap];  // list index of each appended block
+    int32_t app_pool[kListCap];  // its pool block if it still has to be marked, else -1
+    StageBuf<kMcCap> mcb;
+    unsigned int n_list, n_app, n_claim, n_new_wg;
+    unsigned long long pool_base;
+};
+
 __device__ __forceinline__ uint32_t set_hash(uint64_t k) {
     return uint32_t((k * 0x9E3779B97F4A7C15ull) >> 40);
 }
 
-__global__ void __launch_bounds__(kAllocThreads) k_alloc(Dev S, Frame fr, const float *__restrict__ depth,
-                                                         uint32_t frame, int seq, int mark) {
-    __shared__ unsigned long long set[kSetSlots];
-    __shared__ unsigned long long list[kListCap];
-    __shared__ int32_t appended[kListCap];
-    __shared__ uint16_t app_idx[kListCap];  // list index of each appended block
-    __shared__ int32_t app_pool[kListCap];  // its pool block if it still has to be marked, else -1
-    __shared__ StageBuf<kMcCap> mcb;
-    __shared__ unsigned int n_list, n_app, n_claim, n_new_wg;
-    __shared__ unsigned long long pool_base;
+// Allocation (and, with mark, MC-set marking) of the 32x16-pixel tile (tx, ty) for update
+// seq.  Called by all kAllocThreads threads of a workgroup.
+__device__ __forceinline__ void alloc_tile(const Dev &S, const Frame &fr, const float *__restrict__ depth,
+                                           uint32_t frame, int seq, int mark, int tx, int ty, AllocShared &sh) {
+    unsigned long long *set = sh.set;
+    unsigned long long *list = sh.list;
+    int32_t *appended = sh.appended;
+    uint16_t *app_idx = sh.app_idx;
+    int32_t *app_pool = sh.app_pool;
+    StageBuf<kMcCap> &mcb = sh.mcb;
+    unsigned int &n_list = sh.n_list, &n_app = sh.n_app, &n_claim = sh.n_claim, &n_new_wg = sh.n_new_wg;
+    unsigned long long &pool_base = sh.pool_base;
     FrameCounters *fc = &S.C->fc[seq & (kRing - 1)];
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) begin_update(S, seq);
+    if (tx == 0 && ty == 0 && threadIdx.x == 0) begin_update(S, seq);
     for (int i = threadIdx.x; i < kSetSlots; i += kAllocThreads) set[i] = kEmpty;
     if (threadIdx.x == 0) {
         n_list = 0;
@@ -154,8 +172,8 @@ __global__ void __launch_bounds__(kAllocThreads) k_alloc(Dev S, Frame fr, const 
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
     const int lx = lane & 7, ly = lane >> 3;
-    const int u = (blockIdx.x * 4 + (wave & 3)) * 8 + lx;
-    const int v = (blockIdx.y * (kAllocThreads / 256) + (wave >> 2)) * 8 + ly;
+    const int u = (tx * 4 + (wave & 3)) * 8 + lx;
+    const int v = (ty * 2 + (wave >> 2)) * 8 + ly;
     const bool inb = u < fr.W && v < fr.H;
     const float d = inb ? depth[int64_t(v) * fr.W + u] : 0.0f;
     const bool valid = inb && depth_valid(d, fr);
@@ -295,7 +313,7 @@ __global__ void __launch_bounds__(kAllocThreads) k_alloc(Dev S, Frame fr, const 
             n_new_wg = 0;
         }
         __syncthreads();
-        for (unsigned int i = threadIdx.x; i < n_app; i += kAllocThreads) S.touched[pool_base + i] = appended[i];
+        for (unsigned int i = threadIdx.x; i < n_app; i += kAllocThreads) touched_of(S, seq)[pool_base + i] = appended[i];
         if (mark) {  // uniform: MC-set marking, thread per (appended block, e in {0,1}^3)
             const unsigned int items = n_app * 8u;
             for (unsigned int r = 0; r < items; r += kAllocThreads) {
@@ -315,10 +333,10 @@ __global__ void __launch_bounds__(kAllocThreads) k_alloc(Dev S, Frame fr, const 
                 __syncthreads();
                 const unsigned int c = mcb.count;
                 __syncthreads();  // every thread has read the count before it changes again
-                if (c > unsigned(kMcCap - kAllocThreads)) flush_mc(S, fc, mcb);
+                if (c > unsigned(kMcCap - kAllocThreads)) flush_mc(mclist_of(S, seq), fc, mcb);
             }
             __syncthreads();
-            if (mcb.count) flush_mc(S, fc, mcb);  // no thread stages again before this flush
+            if (mcb.count) flush_mc(mclist_of(S, seq), fc, mcb);  // no thread stages again before this flush
         }
         if (s + 1 < n_samples) {  // start a new collection
             for (int i = threadIdx.x; i < kSetSlots; i += kAllocThreads) set[i] = kEmpty;
@@ -331,6 +349,12 @@ __global__ void __launch_bounds__(kAllocThreads) k_alloc(Dev S, Frame fr, const 
         }
         __syncthreads();
     }
+}
+
+__global__ void __launch_bounds__(kAllocThreads) k_alloc(Dev S, Frame fr, const float *__restrict__ depth,
+                                                         uint32_t frame, int seq, int mark) {
+    __shared__ AllocShared sh;
+    alloc_tile(S, fr, depth, frame, seq, mark, int(blockIdx.x), int(blockIdx.y), sh);
 }
 
 __device__ __forceinline__ uint64_t first_lane64(uint64_t v) {
@@ -359,11 +383,12 @@ __global__ void __launch_bounds__(kBlock) k_integrate(Dev S, Frame fr, const flo
     const int lx = lane & 7, ly = lane >> 3;
     const int64_t gw = int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6);
     const int64_t nw = int64_t(gridDim.x) * kWaves;
+    const int32_t *touched = touched_of(S, seq);
     unsigned long long updates = 0;
     Slot cur = {};
-    if (gw < n) cur = S.T[S.touched[gw]];
+    if (gw < n) cur = S.T[touched[gw]];
     for (int64_t t = gw; t < n; t += nw) {
-        const int32_t next_idx = t + nw < n ? S.touched[t + nw] : -1;
+        const int32_t next_idx = t + nw < n ? touched[t + nw] : -1;
         // every lane loaded the same slot: make it wave-uniform (scalar registers)
         const int32_t pool = __builtin_amdgcn_readfirstlane(cur.val);
         int32_t bx, by, bz;
@@ -490,7 +515,7 @@ __global__ void __launch_bounds__(kMarkThreads) k_mc_mark(Dev S, uint32_t frame,
         const int64_t i = b0 + threadIdx.x;
         int32_t target = -1;
         if (i < total) {
-            const Slot *sl = S.T + S.touched[i >> 3];
+            const Slot *sl = S.T + touched_of(S, seq)[i >> 3];
             const int32_t pool = sl->val;
             const int e = int(i & 7);
             if (pool >= 0) {
@@ -507,7 +532,7 @@ __global__ void __launch_bounds__(kMarkThreads) k_mc_mark(Dev S, uint32_t frame,
         __syncthreads();
         const unsigned int c = mb.count;
         __syncthreads();  // every thread has read the count before it changes again
-        if (c > unsigned(kCap - kMarkThreads) || b0 + stride >= total) flush_mc(S, fc, mb);
+        if (c > unsigned(kCap - kMarkThreads) || b0 + stride >= total) flush_mc(mclist_of(S, seq), fc, mb);
     }
 }
 
@@ -592,12 +617,13 @@ __device__ __forceinline__ void mc_block(const Dev &S, int32_t pool, uint64_t ke
 // entries (frame << 32 | pool) at [log_base, log_base + n).
 // Workgroup 0 also folds the integration kernel's n_partials per-workgroup voxel counts
 // into the update's statistics and advances the log length.
-__global__ void __launch_bounds__(kBlock) k_mc_extract(Dev S, int seq, int n_partials, uint32_t frame) {
-    __shared__ unsigned long long red[kWaves];
+// Workgroup wg of n_wg (kBlock threads) of the extraction of update seq.
+__device__ __forceinline__ void extract_wg(const Dev &S, int seq, int n_partials, uint32_t frame, int64_t wg,
+                                           int64_t n_wg, unsigned long long *red) {
     FrameCounters &fcr = S.C->fc[seq & (kRing - 1)];
     const int64_t n = update_set_size(fcr);
     const unsigned long long log_base = fcr.log_base;
-    if (blockIdx.x == 0) {
+    if (wg == 0) {
         unsigned long long v = 0;
         for (int i = threadIdx.x; i < n_partials; i += kBlock) v += S.partial[i];
         v = wave_sum(v);
@@ -615,16 +641,21 @@ __global__ void __launch_bounds__(kBlock) k_mc_extract(Dev S, int seq, int n_par
         }
     }
     const int lane = lane_id();
-    const int64_t gw = int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6);
-    const int64_t nw = int64_t(gridDim.x) * kWaves;
+    const int64_t gw = wg * kWaves + (threadIdx.x >> 6);
+    const int64_t nw = n_wg * kWaves;
     for (int64_t t = gw; t < n; t += nw) {
-        const int32_t pool = S.mclist[t];
+        const int32_t pool = mclist_of(S, seq)[t];
         if (lane_id() == 0 && log_base + t < S.log_cap) S.log[log_base + t] = (uint64_t(frame) << 32) | uint32_t(pool);
         uint32_t out[8];
         mc_block(S, pool, S.pool_key[pool], out);
 #pragma unroll
         for (int j = 0; j < 8; ++j) S.MCV[int64_t(pool) * 512 + lane + 64 * j] = out[j];
     }
+}
+
+__global__ void __launch_bounds__(kBlock) k_mc_extract(Dev S, int seq, int n_partials, uint32_t frame) {
+    __shared__ unsigned long long red[kWaves];
+    extract_wg(S, seq, n_partials, frame, blockIdx.x, gridDim.x, red);
 }
 
 // API form: keys -> uint8 index [n][512] and optional uint8 RGB [n][512][3].
@@ -724,7 +755,7 @@ __global__ void __launch_bounds__(kBlock) k_load_claim(Dev S, const int32_t *key
             }
         }
         const unsigned int pos = wave_append<unsigned int>(append, &fc->n_touched);
-        if (append) S.touched[pos] = int32_t(slot);
+        if (append) touched_of(S, seq)[pos] = int32_t(slot);
         const unsigned long long nm = __ballot(fresh);
         if (nm && lane_id() == __builtin_ctzll(nm)) atomicAdd(&fc->n_new, unsigned(__popcll(nm)));
     }
@@ -768,8 +799,8 @@ __global__ void __launch_bounds__(kBlock) k_keys_of(Dev S, int which, int seq, i
     for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock) {
         uint64_t key;
         if (which == 0) key = S.pool_key[i];
-        else if (which == 1) key = S.T[S.touched[i]].key;
-        else key = S.pool_key[S.mclist[i]];
+        else if (which == 1) key = S.T[touched_of(S, seq)[i]].key;
+        else key = S.pool_key[mclist_of(S, seq)[i]];
         int32_t x, y, z;
         unpack_key(key, x, y, z);
         out[3 * i] = x;
@@ -1005,44 +1036,76 @@ Frame make_frame(const vbh_scene *s, const float *pose) {
 }
 }  // namespace vbh
 
+namespace {
+// Start/stop events for the kernels of update seq if it is one of the timed updates.
+StageTimer *timer_for(vbh_scene *s, int seq) {
+    if (s->timing_period <= 0 || seq % s->timing_period != 0) return nullptr;
+    if (s->ev_free.empty()) {
+        StageTimer t;
+        for (auto &e : t.ev)
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        s->ev_free.push_back(t);
+    }
+    s->ev_pending.push_back(s->ev_free.back());
+    s->ev_free.pop_back();
+    StageTimer *tm = &s->ev_pending.back();
+    tm->ran = 0;
+    return tm;
+}
+
+// Launches a kernel; a timed one gets start/stop events attached to its dispatch (no
+// extra packets between the kernels).
+template <typename... Args, typename F>
+void launch(StageTimer *tm, int stage, hipStream_t st, F kern, dim3 grid, dim3 block, Args... args) {
+    if (tm) {
+        tm->ran |= 1u << stage;
+        hipExtLaunchKernelGGL(kern, grid, block, 0, st, tm->ev[2 * stage], tm->ev[2 * stage + 1], 0, args...);
+    } else {
+        hipLaunchKernelGGL(kern, grid, block, 0, st, args...);
+    }
+}
+
+dim3 alloc_grid(const vbh_scene *s) { return dim3(unsigned((s->p.width + 31) / 32), unsigned((s->p.height + 15) / 16)); }
+}  // namespace
+
 namespace vbh {
 int scene_fuse(vbh_scene *s, const float *d_depth, const uint8_t *d_rgb, const float *pose, uint32_t frame,
                bool with_mc, hipStream_t st) {
     const Frame fr = make_frame(s, pose);
     const int seq = s->seq;
-    // A timed update launches its kernels with start/stop events attached to the dispatch
-    // itself (no extra packets between the kernels).
-    StageTimer *tm = nullptr;
-    if (s->timing_period > 0 && seq % s->timing_period == 0) {
-        if (s->ev_free.empty()) {
-            StageTimer t;
-            for (auto &e : t.ev) VBH_HIP(hipEventCreate(&e));
-            s->ev_free.push_back(t);
-        }
-        s->ev_pending.push_back(s->ev_free.back());
-        s->ev_free.pop_back();
-        tm = &s->ev_pending.back();
-        tm->ran = 0;
-    }
-    auto launch = [&](int stage, auto kern, dim3 grid, dim3 block, auto... args) {
-        if (tm) {
-            tm->ran |= 1u << stage;
-            hipExtLaunchKernelGGL(kern, grid, block, 0, st, tm->ev[2 * stage], tm->ev[2 * stage + 1], 0, args...);
-        } else {
-            hipLaunchKernelGGL(kern, grid, block, 0, st, args...);
-        }
-    };
-    dim3 ga(unsigned((s->p.width + 31) / 32), unsigned((s->p.height + 8 * (kAllocThreads / 256) - 1) /
-                                                        (8 * (kAllocThreads / 256))));
+    StageTimer *tm = timer_for(s, seq);
     const unsigned g = unsigned(s->cus) * 8;
-    const unsigned gi = unsigned(s->cus) * 8;
-    launch(0, k_alloc, ga, dim3(kAllocThreads), s->d, fr, d_depth, frame, seq, int(with_mc));  // marks the MC set
-    launch(1, k_integrate, dim3(gi), dim3(kBlock), s->d, fr, d_depth, d_rgb, seq);
-    if (with_mc) launch(3, k_mc_extract, dim3(g), dim3(kBlock), s->d, seq, int(gi), frame);
+    launch(tm, 0, st, k_alloc, alloc_grid(s), dim3(kAllocThreads), s->d, fr, d_depth, frame, seq, int(with_mc));
+    launch(tm, 1, st, k_integrate, dim3(g), dim3(kBlock), s->d, fr, d_depth, d_rgb, seq);
+    if (with_mc) launch(tm, 3, st, k_mc_extract, dim3(g), dim3(kBlock), s->d, seq, int(g), frame);
     VBH_LAUNCHED();
     s->seq = seq + 1;
     s->last_frame = frame;
     return VBH_OK;
+}
+
+// At most kInFlight frames are enqueued ahead of the device: a deeper queue of launches
+// only stalls submission once the hardware queue is full.
+int scene_fuse_frames(vbh_scene *s, const float *d_depth, const uint8_t *d_rgb, const float *poses, uint32_t first,
+                      int64_t n, hipStream_t st) {
+    constexpr int64_t kStep = 16, kInFlight = 64;
+    const int64_t hw = int64_t(s->p.width) * s->p.height;
+    hipEvent_t ring[kInFlight / kStep] = {};
+    int rc = VBH_OK;
+    for (int64_t i = 0; i < n && rc == VBH_OK; ++i) {
+        if (i % kStep == 0) {
+            hipEvent_t &e = ring[(i / kStep) % (kInFlight / kStep)];
+            if (e && hipEventSynchronize(e) != hipSuccess) rc = VBH_EHIP;
+            if (!e && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) rc = VBH_EHIP;
+            if (rc == VBH_OK && hipEventRecord(e, st) != hipSuccess) rc = VBH_EHIP;
+        }
+        if (rc == VBH_OK)
+            rc = scene_fuse(s, d_depth + i * hw, d_rgb ? d_rgb + i * hw * 3 : nullptr, poses + 12 * i,
+                            first + uint32_t(i), true, st);
+    }
+    for (hipEvent_t e : ring)
+        if (e) (void)hipEventDestroy(e);
+    return rc;
 }
 
 int scene_mc_update(vbh_scene *s, uint32_t frame, hipStream_t st) {
@@ -1084,7 +1147,7 @@ int vbh_scene_create(const vbh_params *p, vbh_scene **out) {
     const uint64_t P = uint64_t(p->pool_blocks);
     s->max_chunks = (p->log_capacity + kChunk - 1) / kChunk + 1;
     const size_t sizes[] = {p->slots * sizeof(Slot), P * 512 * sizeof(float), P * 512 * 4, P * 512 * 4,
-                            P * 8,                  P * 4,                     p->slots * 4, P * 4,
+                            P * 8,                  P * 4,                     2 * p->slots * 4, 2 * P * 4,
                             size_t(p->log_capacity) * 8, size_t(s->max_chunks) * 8, sizeof(Counters), 64 * 8,
                             size_t(kMaxPartials) * 8, P * 64 * 2};
     for (int i = 0; i < 14; ++i) {
@@ -1141,6 +1204,16 @@ int vbh_integrate_frame(vbh_scene *s, const float *d_depth, const uint8_t *d_rgb
     for (int i = 0; i < 12; ++i)
         if (!std::isfinite(pose_c2w[i])) return VBH_EINVAL;
     return vbh::scene_fuse(s, d_depth, d_rgb, pose_c2w, frame_id, true, as_stream(stream));
+}
+
+int vbh_integrate_frames(vbh_scene *s, const float *d_depth, const uint8_t *d_rgb, const float *poses_c2w,
+                         uint32_t first_frame_id, int64_t n, void *stream) {
+    if (!s || n < 0 || (n > 0 && (!d_depth || !poses_c2w)) || first_frame_id == 0 ||
+        first_frame_id <= s->last_frame || uint64_t(first_frame_id) + uint64_t(n > 0 ? n - 1 : 0) > 0xFFFFFFFFull)
+        return VBH_EINVAL;
+    for (int64_t i = 0; i < 12 * n; ++i)
+        if (!std::isfinite(poses_c2w[i])) return VBH_EINVAL;
+    return vbh::scene_fuse_frames(s, d_depth, d_rgb, poses_c2w, first_frame_id, n, as_stream(stream));
 }
 
 int vbh_extract_mc_indices(vbh_scene *s, const int32_t *d_keys, int64_t n, uint8_t *d_mc, uint8_t *d_rgb,

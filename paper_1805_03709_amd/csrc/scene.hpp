@@ -21,7 +21,8 @@ constexpr int kChunk = 2048;  // log entries per workgroup chunk in the paged wa
 constexpr int kRing = 8;      // per-frame counter ring
 constexpr int kMaxPartials = 1 << 16;
 // Start/stop events of the fusion kernels of one timed update; bit i of `ran` is set if
-// stage i was launched.
+// stage i was launched.  Stages: 0 allocation (with MC-set marking), 1 integration,
+// 2 stand-alone MC-set marking, 3 MC extraction.
 constexpr int kStages = 4;
 struct StageTimer {
     std::array<hipEvent_t, 2 * kStages> ev{};
@@ -64,8 +65,8 @@ struct Dev {
                          // observed", bit 8 + z "observed" (W > 0, F not NaN); kept in step with F/W
     uint64_t *pool_key;  // [P]
     uint32_t *mc_stamp;  // [P]
-    int32_t *touched;    // [slots] slot indices
-    int32_t *mclist;     // [P] pool indices of the current update's MC set
+    int32_t *touched;    // [2][slots] slot indices, by update parity
+    int32_t *mclist;     // [2][P] pool indices of an update's MC set, by update parity
     uint64_t *log;       // [L] (frame << 32) | pool
     int64_t *prefix;     // [max_chunks + 1] scratch of the paged walk
     unsigned long long *partial;  // [kMaxPartials] per-workgroup statistics, reduced later
@@ -83,6 +84,16 @@ struct Frame {
     float vs, mu;
     int m_band;
 };
+
+// The touched list and MC list of update `seq`: double-buffered, so that the allocation
+// of one update may run while the previous update's integration and extraction read
+// theirs.
+__device__ __forceinline__ int32_t *touched_of(const Dev &S, int seq) {
+    return S.touched + int64_t(seq & 1) * int64_t(S.mask + 1);
+}
+__device__ __forceinline__ int32_t *mclist_of(const Dev &S, int seq) {
+    return S.mclist + int64_t(seq & 1) * S.pool_cap;
+}
 
 // The depth validity rule: positive and inside [dmin, dmax] (float32 tests).
 __device__ __forceinline__ bool depth_valid(float d, const Frame &f) {
@@ -115,6 +126,10 @@ Frame make_frame(const vbh_scene *s, const float *pose);
 // and log) as update `frame` of the scene; the caller validated the arguments.
 int scene_fuse(vbh_scene *s, const float *d_depth, const uint8_t *d_rgb, const float *pose, uint32_t frame,
                bool with_mc, hipStream_t st);
+// Enqueues n consecutive frames (depth [n][H][W], rgb [n][H][W][3] or null, host poses
+// [n][12], ids first..first+n-1) with their MC updates, as n scene_fuse calls.
+int scene_fuse_frames(vbh_scene *s, const float *d_depth, const uint8_t *d_rgb, const float *poses, uint32_t first,
+                      int64_t n, hipStream_t st);
 // Enqueues the MC update (update-set marking, MC voxels, stamps, log) of the scene's last
 // update, which must have been fused with with_mc = false as update `frame`.
 int scene_mc_update(vbh_scene *s, uint32_t frame, hipStream_t st);

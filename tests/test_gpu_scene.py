@@ -230,3 +230,50 @@ def test_ragged_empty_and_invalid_frames(orc):
     mc_on_identical_input(orc, vol, cam, k2, F2, W2, rgb2, gmc, grgb)
     emc, ergb = G.vbh_extract_mc_indices(to_dev(k2))
     assert np.array_equal(emc.cpu().numpy(), gmc) and np.array_equal(ergb.cpu().numpy(), grgb)
+
+
+def test_multi_frame_form_equals_per_frame_calls(orc):
+    """vbh_integrate_frames against one vbh_integrate_frame call per frame, on the full-size volume:
+    block set, voxel state, MC voxels, update log and statistics bit-exact; then the
+    multi-frame scene against the oracle."""
+    vbh = require_gpu()
+    n = 10
+    say(f"[scene multi-frame] generating {n} full-size frames")
+    _, depth, rgb, poses = configs.full_inputs(range(n))
+    d, c = depth.cuda(), rgb.cuda()
+    params = vbh.make_params(configs.FULL_VOL, configs.FULL_CAM)
+    A, B = vbh.Scene(params), vbh.Scene(params)
+    for f in range(n):
+        A.vbh_integrate_frame(d[f], c[f], poses[f], f + 1)
+    B.vbh_scene_enable_timing(2)
+    B.vbh_integrate_frames(d[:4].contiguous(), c[:4].contiguous(), poses[:4], 1)
+    B.vbh_integrate_frames(d[4:].contiguous(), c[4:].contiguous(), poses[4:], 5)
+    assert A.vbh_scene_status() == 0 and B.vbh_scene_status() == 0
+    ms, timed = B.vbh_scene_timing()
+    assert timed == n // 2 and ms["alloc"] > 0 and ms["integrate"] > 0 and ms["mc_extract"] > 0
+    sa, sb = A.vbh_scene_stats(), B.vbh_scene_stats()
+    for k in ("n_blocks", "log_length", "total_touched", "total_mc", "total_voxel_updates", "n_touched", "n_mc"):
+        assert sa[k] == sb[k], k
+    assert keyset(A.vbh_scene_last_touched()) == keyset(B.vbh_scene_last_touched())
+    assert keyset(A.vbh_scene_last_mc()) == keyset(B.vbh_scene_last_mc())
+    keys, _ = sort_keys(A.vbh_scene_export_blocks().cpu().numpy())
+    assert keyset(keys) == keyset(B.vbh_scene_export_blocks())
+    dk = to_dev(keys)
+    for x, y in zip(A.vbh_scene_read_blocks(dk), B.vbh_scene_read_blocks(dk)):
+        assert torch.equal(x, y)
+    for x, y in zip(A.vbh_stored_mc(dk), B.vbh_stored_mc(dk)):
+        assert torch.equal(x, y)
+    L = sa["log_length"]
+    la = [t.cpu().numpy() for t in A.vbh_scene_log_entries(0, L)]
+    lb = [t.cpu().numpy() for t in B.vbh_scene_log_entries(0, L)]
+    ra = sorted(zip(la[0].tolist(), map(tuple, la[1].tolist())))
+    rb = sorted(zip(lb[0].tolist(), map(tuple, lb[1].tolist())))
+    assert ra == rb and (np.diff(lb[0]) >= 0).all()
+    say(f"  {keys.shape[0]} blocks, {L} log entries identical")
+    with pytest.raises(vbh.VbhError):
+        B.vbh_integrate_frames(d[:1].contiguous(), c[:1].contiguous(), poses[:1], n)  # id not increasing
+    # and the multi-frame form against the oracle
+    O = orc.Scene(configs.FULL_VOL, configs.FULL_CAM)
+    for f in range(n):
+        assert O.integrate(depth[f].numpy(), rgb[f].numpy(), poses[f], f + 1) == 0
+    compare_state(B, O)
