@@ -84,11 +84,16 @@ __device__ __forceinline__ uint64_t home_slot(int32_t x, int32_t y, int32_t z, u
 __device__ __forceinline__ uint64_t ld_key(const Slot *s) {
     return __hip_atomic_load(&s->key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// A value word goes from PENDING to its final value once and is the only datum a reader
+// takes from it, so device-scope relaxed accesses suffice: they are coherent across the
+// XCDs' L2s by themselves.  (Acquire/release would add an L2 invalidate or write-back per
+// access to order other memory, which nothing here needs; data published alongside a
+// value, such as a pool block's key, is only read by later kernels.)
 __device__ __forceinline__ int32_t ld_val(const Slot *s) {
-    return __hip_atomic_load(&s->val, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(&s->val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void st_val(Slot *s, int32_t v) {
-    __hip_atomic_store(&s->val, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&s->val, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ uint64_t cas_key(Slot *s, uint64_t expect, uint64_t desired) {
     return atomicCAS(&s->key, (unsigned long long)expect, (unsigned long long)desired);
