@@ -111,28 +111,35 @@ def hash_bench(vbh, log_phases=True):
         if log_phases and i % 4 == 3:
             log(f"[bench] hash batches generated: {i + 1}")
     out = {}
+    reps = 5
     for kind, name in ((0, "spatial"), (1, "mix64")):
         m = vbh.Map(1 << 25, kind)
         st = torch.empty(dk.shape[0], dtype=torch.int32, device="cuda")
-        e = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
-        torch.cuda.synchronize()
-        e[0].record()
-        m.vbh_insert(dk, dv, st)
-        e[1].record()
-        m.vbh_find(dk, st)
-        e[2].record()
         res = torch.empty(1 << 20, dtype=torch.int32, device="cuda")
-        for ops, k, v in batches:
-            m.vbh_apply(ops, k, v, res)
-        e[3].record()
-        torch.cuda.synchronize()
-        if m.vbh_map_status() != 0:
-            raise RuntimeError("hash map reported an error")
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ins, fnd, mix = [], [], []
+        for rep in range(reps):  # each rep starts from an empty table (cleared outside the timing)
+            m.vbh_map_clear()
+            torch.cuda.synchronize()
+            e[0].record()
+            m.vbh_insert(dk, dv, st)
+            e[1].record()
+            m.vbh_find(dk, st)
+            e[2].record()
+            for ops, k, v in batches:
+                m.vbh_apply(ops, k, v, res)
+            e[3].record()
+            torch.cuda.synchronize()
+            if m.vbh_map_status() != 0:
+                raise RuntimeError("hash map reported an error")
+            ins.append(e[0].elapsed_time(e[1]))
+            fnd.append(e[1].elapsed_time(e[2]))
+            mix.append(e[2].elapsed_time(e[3]))
         n = dk.shape[0]
         nm = sum(b[0].shape[0] for b in batches)
-        out[name] = {"insert_mops": n / e[0].elapsed_time(e[1]) / 1e3,
-                     "find_mops": n / e[1].elapsed_time(e[2]) / 1e3,
-                     "mixed_mops": nm / e[2].elapsed_time(e[3]) / 1e3}
+        out[name] = {"insert_mops": n / float(np.median(ins)) / 1e3,
+                     "find_mops": n / float(np.median(fnd)) / 1e3,
+                     "mixed_mops": nm / float(np.median(mix)) / 1e3, "reps": reps}
         m.close()
         log(f"[bench] hash {name}: {out[name]}")
     return out
