@@ -21,15 +21,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Algorithmic bytes of one MC-set block in the extraction kernel: the sign/observed columns
-# it reads (own 128 B plus the +x/+y/+x+y halo columns, 162 B, for the block and again for
-# its +z neighbours), the 7 neighbour slots it probes (16 B each), its MC-list entry and
-# key (12 B), the 512 colour words it reads and the 512 MC voxels it writes (4 B each).
-MC_BYTES_PER_BLOCK = 2 * (128 + 16 + 16 + 2) + 7 * 16 + 12 + 512 * 4 + 512 * 4
-# Integration: F and W/RGB read and written per updated voxel (16 B), per touched block
-# its slot (16 B) and its sign/observed columns read and written (256 B), per pixel the
-# depth and colour (7 B).
-INT_BYTES_PER_UPDATE, INT_BYTES_PER_BLOCK, INT_BYTES_PER_PIXEL = 16, 16 + 256, 7
+# Algorithmic bytes per unit of work, for the whole-block formulation of each step:
+# integration reads and writes F (4 B) and W+RGB (4 B) of all 512 voxels of a touched
+# block (8 KiB) and reads each pixel's depth (4 B) and colour (3 B); extraction of one
+# MC-set block reads F and W (5 B) of its 729 voxels including the +1 halo and the RGB
+# (3 B) of its 512 voxels, and writes 512 4-byte MC voxels.  The kernels move fewer
+# bytes than this where they can (only updated voxels change, sign bits stand in for F
+# and W in extraction); rocprofv3's measured traffic is reported beside it.
+INT_BYTES_PER_BLOCK, INT_BYTES_PER_PIXEL = 16 * 512, 7
+MC_BYTES_PER_BLOCK = 5 * 729 + 3 * 512 + 4 * 512
 
 
 def log(*a):
@@ -302,8 +302,7 @@ def main():
     # algorithmic bytes per frame (averaged over all K frames)
     hw = 640 * 480
     bytes_frame = {
-        "integrate": (INT_BYTES_PER_UPDATE * stats["total_voxel_updates"] + INT_BYTES_PER_BLOCK *
-                      stats["total_touched"]) / K + INT_BYTES_PER_PIXEL * hw,
+        "integrate": INT_BYTES_PER_BLOCK * stats["total_touched"] / K + INT_BYTES_PER_PIXEL * hw,
         "mc_extract": MC_BYTES_PER_BLOCK * float(stats["total_mc"]) / K,
     }
     dom = max(bytes_frame, key=lambda s: ms_frame[s])

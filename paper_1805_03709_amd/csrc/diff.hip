@@ -409,13 +409,23 @@ __global__ void __launch_bounds__(kBlock) k_integrate_bwd(DiffDev D, Frame fr, C
     xi_flush(D, acc);
 }
 
-__global__ void k_reduce_xi(DiffDev D, int n_part_a, int n_part_b, float *grad_xi) {
+// One workgroup per pose-gradient component i: a fixed-order sum of its per-workgroup
+// partials (rows), strided over the threads, then across the workgroup.
+__global__ void __launch_bounds__(kBlock) k_reduce_xi(DiffDev D, int n_part_a, int n_part_b, float *grad_xi) {
     // partials of k_sample_bwd occupy rows [0, n_part_a), those of k_integrate_bwd
     // rows [n_part_a, n_part_a + n_part_b) (written at an offset)
-    for (int i = threadIdx.x; i < D.F * 6; i += blockDim.x) {
-        double s = 0.0;
-        for (int r = 0; r < n_part_a + n_part_b; ++r) s += D.xi_part[int64_t(r) * D.F * 6 + i];
-        grad_xi[i] = float(s);
+    __shared__ double part[kWaves];
+    const int i = blockIdx.x;
+    const int rows = n_part_a + n_part_b;
+    double s = 0.0;
+    for (int r = threadIdx.x; r < rows; r += kBlock) s += D.xi_part[int64_t(r) * D.F * 6 + i];
+    s = wave_sum(s);
+    if (lane_id() == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kWaves; ++w) t += part[w];
+        grad_xi[i] = float(t);
     }
 }
 
@@ -540,7 +550,7 @@ int vbh_diff_backward(vbh_diff *D, const float *d_depth, const float *h_poses, c
     db.xi_part = D->d.xi_part + int64_t(gs) * D->F * 6;  // integration partials follow
     const unsigned gb = g < unsigned(kMaxWG) ? g : unsigned(kMaxWG);
     k_integrate_bwd<<<gb, kBlock, 0, st>>>(db, fr, cams, d_depth);
-    k_reduce_xi<<<1, 256, 0, st>>>(D->d, int(gs), int(gb), d_grad_xi);
+    k_reduce_xi<<<unsigned(D->F * 6), kBlock, 0, st>>>(D->d, int(gs), int(gb), d_grad_xi);
     k_to_f32<<<g, kBlock, 0, st>>>(D->d.gd64, d_grad_depth, HW * D->F);
     VBH_LAUNCHED();
     return VBH_OK;
