@@ -1,5 +1,6 @@
 // Differentiable form of the fusion path: several depth frames are integrated into a
-// fresh block-hashed volume (the band allocation and integration kernels of scene.hip),
+// fresh block-hashed volume (the band allocation kernel of scene.hip, then the voxel
+// means in float64 below),
 // the loss is L = sum_k F_tri(x_k)^2 over back-projected pixel samples, and the backward
 // pass gives dL/d(depth) per pixel and dL/d(xi) per frame for a left se(3) perturbation
 // T_f = Exp(xi_f) T_f of each camera-to-world pose, xi = (rho; phi).
@@ -20,7 +21,9 @@
 // surface), which would magnify that to ~1e-3 relative.  This path therefore keeps the
 // fusion kernels' float32 decisions (allocation, W, pixels, skips, clamps, cells) but
 // evaluates its values in float64: F64_v = (1/W_v) sum of float64 TSDFs, float64
-// sample points, float64 dL/dF, float64 accumulation (native FP64 atomics).
+// sample points, float64 dL/dF, float64 accumulation (native FP64 atomics).  W_v, the
+// count of observations that pass those decisions, is what the float32 integration
+// would store (no saturation below 255 frames).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -172,9 +175,10 @@ __device__ __forceinline__ void tri_weights(const double *fr, double *w, double 
     }
 }
 
-// One wave per allocated block: the float64 mean of the observed TSDFs of every voxel,
-// revisiting each frame that integrated the block with the fusion kernels' float32
-// decisions (pixel, validity, -trunc skip, +trunc clamp).
+// One wave per allocated block: the float64 mean of the observed TSDFs of every voxel and
+// its weight W (the number of observations), revisiting each frame whose band touched the
+// block with the fusion kernels' float32 decisions (pixel, validity, -trunc skip, +trunc
+// clamp).  This is the volume the loss samples; the float32 integration kernel is not run.
 __global__ void __launch_bounds__(kBlock) k_mean64(DiffDev D, Frame fr, Cams cams, const float *depth) {
     const Dev &S = D.S;
     const unsigned long long pn = S.C->pool_next;
@@ -223,7 +227,10 @@ __global__ void __launch_bounds__(kBlock) k_mean64(DiffDev D, Frame fr, Cams cam
             }
         }
 #pragma unroll
-        for (int j = 0; j < 8; ++j) D.F64[pool * 512 + lane + 64 * j] = cnt[j] ? sum[j] / double(cnt[j]) : 0.0;
+        for (int j = 0; j < 8; ++j) {
+            D.F64[pool * 512 + lane + 64 * j] = cnt[j] ? sum[j] / double(cnt[j]) : 0.0;
+            S.WRGB[pool * 512 + lane + 64 * j] = uint32_t(cnt[j]);  // W (at most kMaxFrames observations)
+        }
     }
 }
 
@@ -511,7 +518,7 @@ int vbh_diff_forward(vbh_diff *D, const float *d_depth, const float *h_poses, co
     const int64_t HW = int64_t(s->p.width) * s->p.height;
     for (int f = 0; f < D->F; ++f) {
         const int seq = s->seq;
-        if (int rc = scene_fuse(s, d_depth + f * HW, nullptr, cams.P[f], uint32_t(f + 1), false, st)) return rc;
+        if (int rc = scene_alloc_only(s, d_depth + f * HW, cams.P[f], uint32_t(f + 1), st)) return rc;
         k_touch_mask<<<g, kBlock, 0, st>>>(D->d, f, seq);
     }
     const Frame fr = make_frame(s, cams.P[0]);

@@ -1108,6 +1108,16 @@ int scene_fuse_frames(vbh_scene *s, const float *d_depth, const uint8_t *d_rgb, 
     return rc;
 }
 
+int scene_alloc_only(vbh_scene *s, const float *d_depth, const float *pose, uint32_t frame, hipStream_t st) {
+    const int seq = s->seq;
+    launch(timer_for(s, seq), 0, st, k_alloc, alloc_grid(s), dim3(kAllocThreads), s->d, make_frame(s, pose), d_depth,
+           frame, seq, 0);
+    VBH_LAUNCHED();
+    s->seq = seq + 1;
+    s->last_frame = frame;
+    return VBH_OK;
+}
+
 int scene_mc_update(vbh_scene *s, uint32_t frame, hipStream_t st) {
     const int seq = s->seq - 1;
     if (seq < 0) return VBH_EINVAL;

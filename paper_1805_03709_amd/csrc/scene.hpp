@@ -130,6 +130,9 @@ int scene_fuse(vbh_scene *s, const float *d_depth, const uint8_t *d_rgb, const f
 // [n][12], ids first..first+n-1) with their MC updates, as n scene_fuse calls.
 int scene_fuse_frames(vbh_scene *s, const float *d_depth, const uint8_t *d_rgb, const float *poses, uint32_t first,
                       int64_t n, hipStream_t st);
+// Enqueues only the band allocation of one frame (touched list, new blocks, no MC set) as
+// update `frame`, for callers that compute the voxel state themselves.
+int scene_alloc_only(vbh_scene *s, const float *d_depth, const float *pose, uint32_t frame, hipStream_t st);
 // Enqueues the MC update (update-set marking, MC voxels, stamps, log) of the scene's last
 // update, which must have been fused with with_mc = false as update `frame`.
 int scene_mc_update(vbh_scene *s, uint32_t frame, hipStream_t st);
