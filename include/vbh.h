@@ -169,6 +169,15 @@ int vbh_integrate_frame(vbh_scene *s, const float *d_depth, const uint8_t *d_rgb
 int vbh_integrate_frames(vbh_scene *s, const float *d_depth, const uint8_t *d_rgb, const float *poses_c2w,
                          uint32_t first_frame_id, int64_t n, void *stream);
 
+/* vbh_integrate_frames for frames in HOST memory (h_depth float32 [n][H*W], h_rgb uint8
+ * [n][H*W*3] or NULL; page-locked memory gives asynchronous copies): each frame is copied
+ * over PCIe, on the caller's stream, into one of two library-owned device buffers and
+ * then fused.  The host buffers must stay valid until the caller's stream has completed
+ * the work; results equal those of vbh_integrate_frames on the same frames.  VBH_ENOMEM
+ * if the two buffers cannot be allocated (first call only). */
+int vbh_integrate_frames_host(vbh_scene *s, const float *h_depth, const uint8_t *h_rgb, const float *poses_c2w,
+                              uint32_t first_frame_id, int64_t n, void *stream);
+
 /* MC voxels (Sec. 4.2) recomputed from the current TSDF for n blocks: d_mc uint8
  * [n*512] case indices (bit k set iff corner k, Lorensen-Cline order (0,0,0) (1,0,0)
  * (1,1,0) (0,1,0) (0,0,1) (1,0,1) (1,1,1) (0,1,1), has F < 0; 0 if any corner lies in a

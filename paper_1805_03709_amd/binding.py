@@ -91,6 +91,7 @@ SIGNATURES = {
     "vbh_scene_destroy": ([_V], None),
     "vbh_integrate_frame": ([_V, _P, _P, C.POINTER(C.c_float), C.c_uint32, _V], C.c_int),
     "vbh_integrate_frames": ([_V, _P, _P, C.POINTER(C.c_float), C.c_uint32, _I64, _V], C.c_int),
+    "vbh_integrate_frames_host": ([_V, _P, _P, C.POINTER(C.c_float), C.c_uint32, _I64, _V], C.c_int),
     "vbh_extract_mc_indices": ([_V, _P, _I64, _P, _P, _V], C.c_int),
     "vbh_stored_mc": ([_V, _P, _I64, _P, _P, _V], C.c_int),
     "vbh_updated_blocks_since": ([_V, _U64, _I64, _P, _P, _P, _V], C.c_int),
@@ -160,6 +161,20 @@ def _ptr(t, dtype=None, n=None, name="tensor"):
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
     if n is not None and t.numel() < n:
+        raise ValueError(f"{name} has {t.numel()} elements, needs {n}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _hptr(t, dtype, n, name):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or t.is_cuda:
+        raise TypeError(f"{name} must be a CPU torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() < n:
         raise ValueError(f"{name} has {t.numel()} elements, needs {n}")
     return C.c_void_p(t.data_ptr())
 
@@ -285,6 +300,17 @@ class Scene:
         _check(lib().vbh_integrate_frames(self.h, _ptr(depth, torch.float32, n * hw, "depth"),
                                           _ptr(rgb, torch.uint8, 3 * n * hw, "rgb"), poses, first_frame_id, n,
                                           _stream()), "vbh_integrate_frames")
+
+    def vbh_integrate_frames_host(self, depth, rgb, poses_c2w, first_frame_id: int):
+        """vbh_integrate_frames for CPU tensors (pin_memory() ones overlap the uploads)."""
+        p = self.params
+        n = int(depth.shape[0]) if depth is not None else 0
+        hw = p.width * p.height
+        P = _poses_f32(poses_c2w, n) if n > 0 else np.zeros((1, 12), np.float32)
+        _check(lib().vbh_integrate_frames_host(self.h, _hptr(depth, torch.float32, n * hw, "depth"),
+                                               _hptr(rgb, torch.uint8, 3 * n * hw, "rgb"),
+                                               P.ctypes.data_as(C.POINTER(C.c_float)), first_frame_id, n, _stream()),
+               "vbh_integrate_frames_host")
 
     def vbh_extract_mc_indices(self, keys, with_rgb=True):
         kp, n = _keys(keys)

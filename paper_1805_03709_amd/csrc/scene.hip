@@ -1108,6 +1108,41 @@ int scene_fuse_frames(vbh_scene *s, const float *d_depth, const uint8_t *d_rgb, 
     return rc;
 }
 
+// Copies go on the caller's stream, in front of each frame's kernels, into one of two
+// device buffers.  (A second stream for the copies, ordered by events, measured slower:
+// the cross-stream waits cost more than the overlap gains.)
+int scene_fuse_frames_host(vbh_scene *s, const float *h_depth, const uint8_t *h_rgb, const float *poses,
+                           uint32_t first, int64_t n, hipStream_t st) {
+    constexpr int64_t kStep = 16, kInFlight = 64;
+    const size_t hw = size_t(s->p.width) * size_t(s->p.height);
+    const size_t dbytes = hw * 4, cbytes = hw * 3, stride = (dbytes + cbytes + 255) & ~size_t(255);
+    for (int b = 0; b < 2; ++b)
+        if (!s->up_buf[b] && hipMalloc(&s->up_buf[b], stride) != hipSuccess) return VBH_ENOMEM;
+    hipEvent_t ring[kInFlight / kStep] = {};
+    int rc = VBH_OK;
+    for (int64_t i = 0; i < n && rc == VBH_OK; ++i) {
+        if (i % kStep == 0) {
+            hipEvent_t &e = ring[(i / kStep) % (kInFlight / kStep)];
+            if (e && hipEventSynchronize(e) != hipSuccess) rc = VBH_EHIP;
+            if (!e && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) rc = VBH_EHIP;
+            if (rc == VBH_OK && hipEventRecord(e, st) != hipSuccess) rc = VBH_EHIP;
+            if (rc != VBH_OK) break;
+        }
+        float *dd = static_cast<float *>(s->up_buf[i & 1]);
+        uint8_t *dc = static_cast<uint8_t *>(s->up_buf[i & 1]) + dbytes;
+        if (hipMemcpyAsync(dd, h_depth + int64_t(i) * int64_t(hw), dbytes, hipMemcpyHostToDevice, st) != hipSuccess ||
+            (h_rgb && hipMemcpyAsync(dc, h_rgb + int64_t(i) * int64_t(hw) * 3, cbytes, hipMemcpyHostToDevice, st) !=
+                          hipSuccess)) {
+            rc = VBH_EHIP;
+            break;
+        }
+        rc = scene_fuse(s, dd, h_rgb ? dc : nullptr, poses + 12 * i, first + uint32_t(i), true, st);
+    }
+    for (hipEvent_t e : ring)
+        if (e) (void)hipEventDestroy(e);
+    return rc;
+}
+
 int scene_alloc_only(vbh_scene *s, const float *d_depth, const float *pose, uint32_t frame, hipStream_t st) {
     const int seq = s->seq;
     launch(timer_for(s, seq), 0, st, k_alloc, alloc_grid(s), dim3(kAllocThreads), s->d, make_frame(s, pose), d_depth,
@@ -1200,6 +1235,8 @@ int vbh_scene_create(const vbh_params *p, vbh_scene **out) {
 
 void vbh_scene_destroy(vbh_scene *s) {
     if (!s) return;
+    for (void *b : s->up_buf)
+        if (b) (void)hipFree(b);
     for (auto *v : {&s->ev_pending, &s->ev_free})
         for (auto &tm : *v)
             for (auto e : tm.ev) (void)hipEventDestroy(e);
@@ -1224,6 +1261,16 @@ int vbh_integrate_frames(vbh_scene *s, const float *d_depth, const uint8_t *d_rg
     for (int64_t i = 0; i < 12 * n; ++i)
         if (!std::isfinite(poses_c2w[i])) return VBH_EINVAL;
     return vbh::scene_fuse_frames(s, d_depth, d_rgb, poses_c2w, first_frame_id, n, as_stream(stream));
+}
+
+int vbh_integrate_frames_host(vbh_scene *s, const float *h_depth, const uint8_t *h_rgb, const float *poses_c2w,
+                              uint32_t first_frame_id, int64_t n, void *stream) {
+    if (!s || n < 0 || (n > 0 && (!h_depth || !poses_c2w)) || first_frame_id == 0 ||
+        first_frame_id <= s->last_frame || uint64_t(first_frame_id) + uint64_t(n > 0 ? n - 1 : 0) > 0xFFFFFFFFull)
+        return VBH_EINVAL;
+    for (int64_t i = 0; i < 12 * n; ++i)
+        if (!std::isfinite(poses_c2w[i])) return VBH_EINVAL;
+    return vbh::scene_fuse_frames_host(s, h_depth, h_rgb, poses_c2w, first_frame_id, n, as_stream(stream));
 }
 
 int vbh_extract_mc_indices(vbh_scene *s, const int32_t *d_keys, int64_t n, uint8_t *d_mc, uint8_t *d_rgb,

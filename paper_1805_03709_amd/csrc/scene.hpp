@@ -115,6 +115,9 @@ struct vbh_scene {
     uint32_t last_frame = 0;
     void *mem[14] = {};
     int timing_period = 0;  // time the kernels of every n-th update (0: off)
+    // the host-input multi-frame form's two device frame buffers (depth then colour),
+    // allocated on first use
+    void *up_buf[2] = {};
     std::vector<vbh::StageTimer> ev_pending, ev_free;
 };
 
@@ -130,6 +133,10 @@ int scene_fuse(vbh_scene *s, const float *d_depth, const uint8_t *d_rgb, const f
 // [n][12], ids first..first+n-1) with their MC updates, as n scene_fuse calls.
 int scene_fuse_frames(vbh_scene *s, const float *d_depth, const uint8_t *d_rgb, const float *poses, uint32_t first,
                       int64_t n, hipStream_t st);
+// The same for frames in host memory: each frame is copied into one of two device buffers
+// on `st` before its kernels.
+int scene_fuse_frames_host(vbh_scene *s, const float *h_depth, const uint8_t *h_rgb, const float *poses,
+                           uint32_t first, int64_t n, hipStream_t st);
 // Enqueues only the band allocation of one frame (touched list, new blocks, no MC set) as
 // update `frame`, for callers that compute the voxel state themselves.
 int scene_alloc_only(vbh_scene *s, const float *d_depth, const float *pose, uint32_t frame, hipStream_t st);

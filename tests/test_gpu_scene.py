@@ -232,25 +232,9 @@ def test_ragged_empty_and_invalid_frames(orc):
     assert np.array_equal(emc.cpu().numpy(), gmc) and np.array_equal(ergb.cpu().numpy(), grgb)
 
 
-def test_multi_frame_form_equals_per_frame_calls(orc):
-    """vbh_integrate_frames against one vbh_integrate_frame call per frame, on the full-size volume:
-    block set, voxel state, MC voxels, update log and statistics bit-exact; then the
-    multi-frame scene against the oracle."""
-    vbh = require_gpu()
-    n = 10
-    say(f"[scene multi-frame] generating {n} full-size frames")
-    _, depth, rgb, poses = configs.full_inputs(range(n))
-    d, c = depth.cuda(), rgb.cuda()
-    params = vbh.make_params(configs.FULL_VOL, configs.FULL_CAM)
-    A, B = vbh.Scene(params), vbh.Scene(params)
-    for f in range(n):
-        A.vbh_integrate_frame(d[f], c[f], poses[f], f + 1)
-    B.vbh_scene_enable_timing(2)
-    B.vbh_integrate_frames(d[:4].contiguous(), c[:4].contiguous(), poses[:4], 1)
-    B.vbh_integrate_frames(d[4:].contiguous(), c[4:].contiguous(), poses[4:], 5)
-    assert A.vbh_scene_status() == 0 and B.vbh_scene_status() == 0
-    ms, timed = B.vbh_scene_timing()
-    assert timed == n // 2 and ms["alloc"] > 0 and ms["integrate"] > 0 and ms["mc_extract"] > 0
+def same_scene(A, B):
+    """Bit-exact equality of two scenes: statistics, last touched/MC sets, block set, voxel
+    state, MC voxels and the update log (a multiset per frame, frames in order)."""
     sa, sb = A.vbh_scene_stats(), B.vbh_scene_stats()
     for k in ("n_blocks", "log_length", "total_touched", "total_mc", "total_voxel_updates", "n_touched", "n_mc"):
         assert sa[k] == sb[k], k
@@ -270,6 +254,28 @@ def test_multi_frame_form_equals_per_frame_calls(orc):
     rb = sorted(zip(lb[0].tolist(), map(tuple, lb[1].tolist())))
     assert ra == rb and (np.diff(lb[0]) >= 0).all()
     say(f"  {keys.shape[0]} blocks, {L} log entries identical")
+
+
+def test_multi_frame_form_equals_per_frame_calls(orc):
+    """vbh_integrate_frames against one vbh_integrate_frame call per frame, on the full-size volume:
+    block set, voxel state, MC voxels, update log and statistics bit-exact; then the
+    multi-frame scene against the oracle."""
+    vbh = require_gpu()
+    n = 10
+    say(f"[scene multi-frame] generating {n} full-size frames")
+    _, depth, rgb, poses = configs.full_inputs(range(n))
+    d, c = depth.cuda(), rgb.cuda()
+    params = vbh.make_params(configs.FULL_VOL, configs.FULL_CAM)
+    A, B = vbh.Scene(params), vbh.Scene(params)
+    for f in range(n):
+        A.vbh_integrate_frame(d[f], c[f], poses[f], f + 1)
+    B.vbh_scene_enable_timing(2)
+    B.vbh_integrate_frames(d[:4].contiguous(), c[:4].contiguous(), poses[:4], 1)
+    B.vbh_integrate_frames(d[4:].contiguous(), c[4:].contiguous(), poses[4:], 5)
+    assert A.vbh_scene_status() == 0 and B.vbh_scene_status() == 0
+    ms, timed = B.vbh_scene_timing()
+    assert timed == n // 2 and ms["alloc"] > 0 and ms["integrate"] > 0 and ms["mc_extract"] > 0
+    same_scene(A, B)
     with pytest.raises(vbh.VbhError):
         B.vbh_integrate_frames(d[:1].contiguous(), c[:1].contiguous(), poses[:1], n)  # id not increasing
     # and the multi-frame form against the oracle
@@ -277,3 +283,24 @@ def test_multi_frame_form_equals_per_frame_calls(orc):
     for f in range(n):
         assert O.integrate(depth[f].numpy(), rgb[f].numpy(), poses[f], f + 1) == 0
     compare_state(B, O)
+
+
+def test_host_input_frames_equal_device_input():
+    """vbh_integrate_frames_host (frames in pinned host memory, uploaded into two device
+    buffers in front of each frame's kernels), split over two calls, against
+    vbh_integrate_frames on device copies of the same frames: bit-exact."""
+    vbh = require_gpu()
+    n = 7
+    say(f"[scene host input] generating {n} full-size frames")
+    _, depth, rgb, poses = configs.full_inputs(range(n))
+    params = vbh.make_params(configs.FULL_VOL, configs.FULL_CAM)
+    A, B = vbh.Scene(params), vbh.Scene(params)
+    A.vbh_integrate_frames(depth.cuda(), rgb.cuda(), poses, 1)
+    hd, hc = depth.contiguous().pin_memory(), rgb.contiguous().pin_memory()
+    B.vbh_integrate_frames_host(hd[:3], hc[:3], poses[:3], 1)
+    B.vbh_integrate_frames_host(hd[3:], hc[3:], poses[3:], 4)
+    torch.cuda.synchronize()
+    assert A.vbh_scene_status() == 0 and B.vbh_scene_status() == 0
+    same_scene(A, B)
+    with pytest.raises(TypeError):
+        B.vbh_integrate_frames_host(depth[:1].cuda(), None, poses[:1], n + 1)  # device tensor refused
