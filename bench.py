@@ -124,7 +124,8 @@ def h2d_fusion(vbh, depth, rgb, traj, K):
 
 
 def hash_bench(vbh, log_phases=True):
-    """Hash map Mops/s: bulk insert/find of 2^24 keys into 2^25 slots, 16 mixed 1M batches."""
+    """Hash map Mops/s: bulk insert/find of 2^24 keys into 2^25 slots, 16 mixed 1M batches,
+    for the open-addressing map and the chained design."""
     import numpy as np
     import torch
     import datagen
@@ -138,8 +139,13 @@ def hash_bench(vbh, log_phases=True):
             log(f"[bench] hash batches generated: {i + 1}")
     out = {}
     reps = 5
-    for kind, name in ((0, "spatial"), (1, "mix64")):
-        m = vbh.Map(1 << 25, kind)
+    # the open-addressing map (2^25 slots) and the paper's chained design in the same
+    # memory (2^24 buckets + 2^24 excess entries), on identical batches
+    designs = ((0, "spatial", lambda k: vbh.Map(1 << 25, k)), (1, "mix64", lambda k: vbh.Map(1 << 25, k)),
+               (0, "chained_spatial", lambda k: vbh.ChainedMap(1 << 24, 1 << 24, k)),
+               (1, "chained_mix64", lambda k: vbh.ChainedMap(1 << 24, 1 << 24, k)))
+    for kind, name, make in designs:
+        m = make(kind)
         st = torch.empty(dk.shape[0], dtype=torch.int32, device="cuda")
         res = torch.empty(1 << 20, dtype=torch.int32, device="cuda")
         e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]

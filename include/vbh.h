@@ -75,6 +75,18 @@ typedef struct vbh_map vbh_map;
 
 /* slots: power of two in [64, 2^31].  Allocates 16 B per slot on the current device. */
 int vbh_map_create(uint64_t slots, int32_t hash_kind, vbh_map **out);
+/* The paper's own chained design (Sec. 5, first paragraph and Insertion/Removal): a
+ * bucket array plus linked-list excess entries reached through per-entry links, a stack
+ * of free excess entries, per-entry occupancy flags and locks, and non-blocking attempts
+ * retried until they succeed, under the invariant that entry positions and links are
+ * preserved.  Every other vbh_map_* / vbh_insert / vbh_find / vbh_erase / vbh_apply call
+ * accepts the handle with the same semantics, except that vbh_map_size reports no
+ * tombstones and vbh_map_rebuild does nothing.
+ *   buckets: power of two in [64, 2^27]; excess: list entries, buckets + excess < 2^28.
+ *   Allocates 16 B per entry plus 4 B per excess entry and 4 B per entry of bookkeeping.
+ * Capacity: a key fails with VBH_EFULL_TABLE when its bucket is taken and no excess
+ * entry is free.  Entries emptied by a batch are reused from the next batch on. */
+int vbh_map_create_chained(uint64_t buckets, uint64_t excess, int32_t hash_kind, vbh_map **out);
 void vbh_map_destroy(vbh_map *m);
 
 /* Insert-if-absent (Sec. 5, Insertion).  d_status[i] = 1 inserted, 0 already present

@@ -37,14 +37,18 @@ class DiffFusion:
     """Owns a vbh_diff handle (a scene plus gradient buffers) on the current device."""
 
     def __init__(self, params: vbh_params, n_frames: int):
+        self._L = lib()
         h = C.c_void_p()
         _check(lib().vbh_diff_create(C.byref(params), n_frames, C.byref(h)), "vbh_diff_create")
         self.h, self.params, self.n_frames = h, params, n_frames
 
     def close(self):
-        if getattr(self, "h", None):
-            lib().vbh_diff_destroy(self.h)
-            self.h = None
+        # the library object is held by the instance: module globals may already be gone
+        # when this runs at interpreter exit
+        L = getattr(self, "_L", None)
+        if getattr(self, "h", None) and L is not None:
+            L.vbh_diff_destroy(self.h)
+        self.h = None
 
     __del__ = close
 

@@ -77,6 +77,7 @@ SIGNATURES = {
     "vbh_strerror": ([C.c_int], C.c_char_p),
     "vbh_version": ([], C.c_int),
     "vbh_map_create": ([_U64, _I32, C.POINTER(_V)], C.c_int),
+    "vbh_map_create_chained": ([_U64, _U64, _I32, C.POINTER(_V)], C.c_int),
     "vbh_map_destroy": ([_V], None),
     "vbh_insert": ([_V, _P, _P, _I64, _P, _V], C.c_int),
     "vbh_find": ([_V, _P, _I64, _P, _V], C.c_int),
@@ -198,14 +199,18 @@ class Map:
     """Concurrent int3 -> int32 hash map on the device (vbh_map_*)."""
 
     def __init__(self, slots: int, hash_kind: int = VBH_HASH_SPATIAL):
+        self._L = lib()
         h = C.c_void_p()
         _check(lib().vbh_map_create(slots, hash_kind, C.byref(h)), "vbh_map_create")
         self.h, self.slots = h, slots
 
     def close(self):
-        if getattr(self, "h", None):
-            lib().vbh_map_destroy(self.h)
-            self.h = None
+        # the library object is held by the instance: module globals may already be gone
+        # when this runs at interpreter exit
+        L = getattr(self, "_L", None)
+        if getattr(self, "h", None) and L is not None:
+            L.vbh_map_destroy(self.h)
+        self.h = None
 
     __del__ = close
 
@@ -259,6 +264,17 @@ class Map:
         return int(lib().vbh_map_status(self.h, _stream()))
 
 
+class ChainedMap(Map):
+    """The paper's chained design behind the same calls (vbh_map_create_chained):
+    `buckets` buckets plus `excess` linked-list entries."""
+
+    def __init__(self, buckets: int, excess: int, hash_kind: int = VBH_HASH_SPATIAL):
+        self._L = lib()
+        h = C.c_void_p()
+        _check(lib().vbh_map_create_chained(buckets, excess, hash_kind, C.byref(h)), "vbh_map_create_chained")
+        self.h, self.slots, self.excess = h, buckets, excess
+
+
 def make_params(vol, cam, hash_kind: int = VBH_HASH_SPATIAL) -> vbh_params:
     return vbh_params(vol.slots, vol.pool_blocks, vol.log_capacity, vol.voxel_size, vol.trunc,
                       cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy, vol.depth_min,
@@ -270,14 +286,18 @@ class Scene:
 
     def __init__(self, params: vbh_params):
         self.params = params
+        self._L = lib()
         h = C.c_void_p()
         _check(lib().vbh_scene_create(C.byref(params), C.byref(h)), "vbh_scene_create")
         self.h = h
 
     def close(self):
-        if getattr(self, "h", None):
-            lib().vbh_scene_destroy(self.h)
-            self.h = None
+        # the library object is held by the instance: module globals may already be gone
+        # when this runs at interpreter exit
+        L = getattr(self, "_L", None)
+        if getattr(self, "h", None) and L is not None:
+            L.vbh_scene_destroy(self.h)
+        self.h = None
 
     __del__ = close
 
@@ -401,14 +421,18 @@ class Server:
     def __init__(self, scene: Scene, arena_bytes: int, max_inflight: int = 256, n_streams: int = 4,
                  n_clients: int = 64, max_batch: int = 64):
         self.cfg = vbh_server_config(arena_bytes, max_inflight, n_streams, n_clients, max_batch)
+        self._L = lib()
         h = C.c_void_p()
         _check(lib().vbh_server_create(scene.h, C.byref(self.cfg), C.byref(h)), "vbh_server_create")
         self.h, self.scene = h, scene
 
     def close(self):
-        if getattr(self, "h", None):
-            lib().vbh_server_destroy(self.h)
-            self.h = None
+        # the library object is held by the instance: module globals may already be gone
+        # when this runs at interpreter exit
+        L = getattr(self, "_L", None)
+        if getattr(self, "h", None) and L is not None:
+            L.vbh_server_destroy(self.h)
+        self.h = None
 
     __del__ = close
 

@@ -1,12 +1,15 @@
 // Concurrent GPU hash map (Sec. 5: retrieval, insertion, removal) - kernels and C ABI.
 //
 // One device thread per operation; a batch is one launch.  See device.hpp for the
-// probing protocol and why every operation completes below capacity.
+// probing protocol and why every operation completes below capacity.  A map created by
+// vbh_map_create_chained holds the paper's chained design instead (chain.hip); every
+// other entry point dispatches on which of the two a handle holds.
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>
 #include <new>
 
+#include "chain.hpp"
 #include "device.hpp"
 #include "host.hpp"
 #include "vbh.h"
@@ -19,6 +22,7 @@ struct vbh_map {
     int hash_kind = 0;
     uint32_t *err = nullptr;        // sticky error bits
     unsigned long long *cnt = nullptr;  // [0] live, [1] tombstones (scratch for size/export)
+    ChainMap *chain = nullptr;          // set for the chained design (then table is unused)
 };
 
 namespace {
@@ -128,6 +132,7 @@ int batch(vbh_map *m, int opc, const uint8_t *ops, const int32_t *keys, const in
     if (opc < 0 && n > 0 && !ops) return VBH_EINVAL;
     if (n == 0) return VBH_OK;
     hipStream_t st = as_stream(stream);
+    if (m->chain) return chain_batch(m->chain, m->hash_kind, opc, ops, keys, vals, n, out, m->err, st);
     const unsigned g = grid_for(n, kBlock);
     const uint64_t mask = m->slots - 1;
     switch (opc) {
@@ -194,8 +199,32 @@ int vbh_map_create(uint64_t slots, int32_t hash_kind, vbh_map **out) {
     return VBH_OK;
 }
 
+int vbh_map_create_chained(uint64_t buckets, uint64_t excess, int32_t hash_kind, vbh_map **out) {
+    if (!out || !is_pow2(buckets) || buckets < 64 || excess > kChainMaxEntries ||
+        buckets + excess > kChainMaxEntries || hash_kind < 0 || hash_kind > 1)
+        return VBH_EINVAL;
+    *out = nullptr;
+    vbh_map *m = new (std::nothrow) vbh_map();
+    if (!m) return VBH_ENOMEM;
+    m->slots = buckets;
+    m->hash_kind = hash_kind;
+    if (chain_create(buckets, excess, &m->chain) != VBH_OK || hipMalloc(&m->err, 256) != hipSuccess) {
+        vbh_map_destroy(m);
+        return VBH_ENOMEM;
+    }
+    m->cnt = reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(m->err) + 64);
+    if (hipMemset(m->err, 0, 256) != hipSuccess || chain_clear(m->chain, nullptr) != VBH_OK ||
+        hipDeviceSynchronize() != hipSuccess) {
+        vbh_map_destroy(m);
+        return VBH_EHIP;
+    }
+    *out = m;
+    return VBH_OK;
+}
+
 void vbh_map_destroy(vbh_map *m) {
     if (!m) return;
+    if (m->chain) chain_destroy(m->chain);
     if (m->table) (void)hipFree(m->table);
     if (m->err) (void)hipFree(m->err);
     delete m;
@@ -220,7 +249,11 @@ int vbh_map_size(vbh_map *m, int64_t *h_live, int64_t *h_tombstones, void *strea
     if (!m) return VBH_EINVAL;
     hipStream_t st = as_stream(stream);
     k_zero_u64<<<1, 64, 0, st>>>(m->cnt, 2);
-    k_count<<<grid_for(int64_t(m->slots), kBlock, 2048), kBlock, 0, st>>>(m->table, m->slots, m->cnt);
+    if (m->chain) {
+        if (chain_count(m->chain, m->cnt, st) != VBH_OK) return VBH_EHIP;
+    } else {
+        k_count<<<grid_for(int64_t(m->slots), kBlock, 2048), kBlock, 0, st>>>(m->table, m->slots, m->cnt);
+    }
     VBH_LAUNCHED();
     unsigned long long h[2];
     VBH_HIP(hipMemcpyAsync(h, m->cnt, sizeof(h), hipMemcpyDeviceToHost, st));
@@ -234,8 +267,12 @@ int vbh_map_export(vbh_map *m, int32_t *d_keys, int32_t *d_vals, int64_t cap, in
     if (!m || cap < 0 || (cap > 0 && !d_keys)) return VBH_EINVAL;
     hipStream_t st = as_stream(stream);
     k_zero_u64<<<1, 64, 0, st>>>(m->cnt, 2);
-    k_export<<<grid_for(int64_t(m->slots), kBlock, 4096), kBlock, 0, st>>>(m->table, m->slots, d_keys, d_vals, cap,
-                                                                            m->cnt);
+    if (m->chain) {
+        if (chain_export(m->chain, d_keys, d_vals, cap, m->cnt, st) != VBH_OK) return VBH_EHIP;
+    } else {
+        k_export<<<grid_for(int64_t(m->slots), kBlock, 4096), kBlock, 0, st>>>(m->table, m->slots, d_keys, d_vals,
+                                                                                cap, m->cnt);
+    }
     VBH_LAUNCHED();
     unsigned long long h = 0;
     VBH_HIP(hipMemcpyAsync(&h, m->cnt, sizeof(h), hipMemcpyDeviceToHost, st));
@@ -246,6 +283,7 @@ int vbh_map_export(vbh_map *m, int32_t *d_keys, int32_t *d_vals, int64_t cap, in
 
 int vbh_map_rebuild(vbh_map *m, void *stream) {
     if (!m) return VBH_EINVAL;
+    if (m->chain) return VBH_OK;  // no tombstones: emptied entries are reused directly
     hipStream_t st = as_stream(stream);
     Slot *fresh = nullptr;
     if (hipMalloc(&fresh, m->slots * sizeof(Slot)) != hipSuccess) return VBH_ENOMEM;
@@ -266,6 +304,7 @@ int vbh_map_rebuild(vbh_map *m, void *stream) {
 
 int vbh_map_clear(vbh_map *m, void *stream) {
     if (!m) return VBH_EINVAL;
+    if (m->chain) return chain_clear(m->chain, as_stream(stream));
     return launch_init(m->table, m->slots, as_stream(stream));
 }
 
