@@ -177,6 +177,100 @@ def hash_bench(vbh, log_phases=True):
     return out
 
 
+def bandwidth_bench(vbh, depth, rgb, traj, n_frames=300, fps=30.0, rate=100.0, sizes=(128, 256, 512, 1024),
+                    drain_s=60.0, tsdf_sample=16):
+    """Synthetic analogue of the paper's bandwidth table: the first n_frames of the
+    sequence are fused at `fps` while benchmark clients request k updated MC blocks at
+    `rate` Hz (one client per k, each from its own cursor) until the model is streamed.
+    Every MC packet is built and zstd-compressed (level 1); bandwidth is compressed bytes
+    per 1-s window.  The TSDF stream sends, unlimited, every block updated since its last
+    step in 512-block packets of 12-byte voxels; its bytes are the exact block counts
+    times the compressed bytes per block of 1 in `tsdf_sample` packets (compressing all
+    of them would take minutes of host time)."""
+    import numpy as np
+    import torch
+    from datagen import configs
+    from paper_1805_03709_amd import packets
+    S = vbh.Scene(vbh.make_params(configs.FULL_VOL, configs.FULL_CAM))
+    n_frames = min(n_frames, depth.shape[0])
+    cur = {k: 0 for k in sizes}
+    sent = {k: [] for k in sizes}     # (time, compressed bytes, blocks)
+    done = {k: None for k in sizes}
+    tsdf_cur, tsdf_steps, tsdf_sampled = 0, [], [0, 0]  # sampled: [compressed bytes, blocks]
+    fused, step, i = 0, 1.0 / rate, 0
+    t_host = time.perf_counter()
+    while any(v is None for v in done.values()):
+        t = i * step
+        if t > n_frames / fps + drain_s:
+            break
+        due = min(n_frames, int(t * fps) + 1)
+        while fused < due:
+            S.vbh_integrate_frame(depth[fused], rgb[fused], traj[fused], fused + 1)
+            fused += 1
+        for k in sizes:
+            if done[k] is not None:
+                continue
+            keys, meta = S.vbh_updated_blocks_since(cur[k], k)
+            cnt, nxt = (int(v) for v in meta.tolist())
+            if cnt:
+                kk = keys[:cnt].contiguous()
+                mc, c3 = S.vbh_stored_mc(kk)
+                mc, c3 = mc.cpu().numpy().astype(np.uint32), c3.cpu().numpy().astype(np.uint32)
+                packed = mc | (c3[..., 0] << 8) | (c3[..., 1] << 16) | (c3[..., 2] << 24)
+                z = packets.zstd_compress(packets.mc_packet(kk.cpu().numpy(), packed))
+                sent[k].append((t, len(z), cnt))
+            cur[k] = nxt
+            if fused == n_frames and cnt < k:
+                done[k] = t
+        if fused < n_frames or i % int(rate) == 0:
+            keys, meta = S.vbh_updated_blocks_since(tsdf_cur, 1 << 22)
+            cnt, nxt = (int(v) for v in meta.tolist())
+            tsdf_steps.append((t, cnt))
+            if cnt and len(tsdf_steps) % tsdf_sample == 1:
+                kk = keys[:min(cnt, 512)].contiguous()
+                F, Wt, c3, found = S.vbh_scene_read_blocks(kk)
+                z = packets.zstd_compress(packets.tsdf_packet(kk.cpu().numpy(), F.cpu().numpy(), Wt.cpu().numpy(),
+                                                              c3.cpu().numpy()))
+                tsdf_sampled[0] += len(z)
+                tsdf_sampled[1] += kk.shape[0]
+            tsdf_cur = nxt
+        if i % int(5 * rate) == 0:
+            log(f"[bench] bandwidth: simulated {t:.0f} s, {fused} frames fused, "
+                f"{time.perf_counter() - t_host:.1f} s host time")
+        i += 1
+    if S.vbh_scene_status() != 0:
+        raise RuntimeError("scene reported an error during the bandwidth run")
+
+    def windows(events, end):
+        nwin = max(1, int(np.ceil(end)))
+        acc = np.zeros(nwin)
+        for tt, b in events:
+            acc[min(int(tt), nwin - 1)] += b
+        mbit = acc * 8 / 1e6
+        return float(mbit.mean()), float(mbit.max())
+
+    out = {"workload": f"first {n_frames} frames of the 640x480 sequence fused at {fps:g} Hz, 5 mm voxels, "
+                       f"2 cm truncation; requests at {rate:g} Hz; zstd level 1",
+           "model_blocks": S.vbh_scene_stats()["n_blocks"], "mc": {}}
+    for k in sizes:
+        ev = sent[k]
+        end = done[k] if done[k] is not None else n_frames / fps + drain_s
+        mean, mx = windows([(tt, b) for tt, b, _ in ev], end)
+        nb = sum(c for _, _, c in ev)
+        out["mc"][str(k)] = {"mean_mbit_s": mean, "max_mbit_s": mx, "complete_s": done[k], "blocks_sent": nb,
+                             "bytes_per_block": sum(b for _, b, _ in ev) / max(nb, 1)}
+    bpb = tsdf_sampled[0] / max(tsdf_sampled[1], 1)
+    end = n_frames / fps
+    mean, mx = windows([(tt, c * bpb) for tt, c in tsdf_steps if tt < end], end)
+    out["tsdf_512"] = {"mean_mbit_s": mean, "max_mbit_s": mx, "bytes_per_block": bpb,
+                       "blocks_sent": sum(c for _, c in tsdf_steps), "sampled_blocks": tsdf_sampled[1],
+                       "uncompressed_bytes_per_block": packets.TSDF_BLOCK_BYTES}
+    out["mc_vs_tsdf_bytes_per_block"] = out["mc"]["512"]["bytes_per_block"] / max(bpb, 1e-9)
+    out["host_seconds"] = time.perf_counter() - t_host
+    S.close()
+    return out
+
+
 def diff_bench(vbh, reps=5):
     """Differentiable form on 16 frames of the 640x480 sequence (2 cm voxels, 8 cm
     truncation, 100k samples): forward and backward kernel time (torch events on the
@@ -296,6 +390,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-diff", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-bandwidth", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--timing-period", type=int, default=4,
@@ -365,6 +460,10 @@ def main():
     log("[bench] fusion with per-frame host-to-device upload")
     result["fusion_with_h2d"] = h2d_fusion(vbh, depth, rgb, traj, min(K, 500))
     log(f"[bench] {result['fusion_with_h2d']}")
+    if not args.no_bandwidth:
+        log("[bench] streaming bandwidth (MC packets vs TSDF packets)")
+        result["bandwidth"] = bandwidth_bench(vbh, depth, rgb, traj)
+        log(f"[bench] bandwidth: {result['bandwidth']}")
     del depth
     if not args.no_hash:
         log("[bench] hash map phase")
