@@ -40,6 +40,8 @@ def lib():
             "orc_export_blocks": ([vp, i32p, i64], i64),
             "orc_read_blocks": ([vp, i32p, i64, f64p, u8p, u8p, i32p], C.c_int),
             "orc_write_blocks": ([vp, i32p, i64, f32p, u8p, u8p, C.c_uint32], C.c_int),
+            "orc_reset_blocks": ([vp, i32p, i64, C.c_uint32, C.c_void_p], C.c_int),
+            "orc_visible_blocks": ([vp, f32p, i32p, i64], i64),
             "orc_extract_mc": ([vp, i32p, i64, u8p, u8p], C.c_int),
             "orc_stored_mc": ([vp, i32p, i64, u8p, u8p], C.c_int),
             "orc_updated_since": ([vp, C.c_uint64, i64, i32p, C.c_void_p], i64),
@@ -194,6 +196,20 @@ class Scene:
         W = np.ascontiguousarray(W, np.uint8)
         c = None if rgb is None else np.ascontiguousarray(rgb, np.uint8)
         return lib().orc_write_blocks(self.h, _p(k), n, _p(F), _p(W), _p(c), frame_id)
+
+    def reset_blocks(self, keys, frame_id: int):
+        """Returns (status, number of distinct blocks reset)."""
+        k, n = _keys(keys)
+        cnt = C.c_int64()
+        rc = lib().orc_reset_blocks(self.h, _p(k), n, frame_id, C.byref(cnt))
+        return rc, cnt.value
+
+    def visible_blocks(self, pose):
+        P = np.ascontiguousarray(np.asarray(pose, np.float32).reshape(-1)[:12])
+        n = lib().orc_visible_blocks(self.h, _p(P), None, 0)
+        k = np.empty((max(n, 1), 3), np.int32)
+        lib().orc_visible_blocks(self.h, _p(P), _p(k), n)
+        return k[:n]
 
     def extract_mc(self, keys):
         k, n = _keys(keys)

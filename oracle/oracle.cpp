@@ -395,6 +395,61 @@ int orc_write_blocks(void *s, const int32_t *keys, int64_t n, const float *F, co
     return S.error;
 }
 
+// Scene reset (Sec. 4.1, quasi-static scenes): each listed block that exists loses its
+// reconstruction - distance, weight and colour of all its voxels become zero, so it reads
+// as never observed - and the MC voxels of the reset blocks and of their seven negative
+// neighbours are recomputed and logged as update frame_id, which is how the change
+// reaches the clients.  Absent keys are skipped; no block is allocated.
+int orc_reset_blocks(void *s, const int32_t *keys, int64_t n, uint32_t frame_id, int64_t *n_reset) {
+    Scene &S = *static_cast<Scene *>(s);
+    if (frame_id == 0 || frame_id <= S.last_frame) return ORC_EINVAL;
+    S.last_frame = frame_id;
+    std::vector<uint64_t> changed;
+    for (int64_t i = 0; i < n; ++i) {
+        const int32_t *k = keys + 3 * i;
+        if (!key_in_range(k[0], k[1], k[2])) { S.error = ORC_EINVAL; continue; }
+        const uint64_t key = pack(k[0], k[1], k[2]);
+        Blk *b = S.get(key);
+        if (!b) continue;
+        for (int l = 0; l < 512; ++l) b->F[l] = 0.0;
+        std::memset(b->W, 0, sizeof(b->W));
+        std::memset(b->C, 0, sizeof(b->C));
+        changed.push_back(key);
+    }
+    std::sort(changed.begin(), changed.end());
+    changed.erase(std::unique(changed.begin(), changed.end()), changed.end());
+    if (n_reset) *n_reset = int64_t(changed.size());
+    S.last_touched = changed;
+    S.last_new.clear();
+    mc_update(S, changed, frame_id);
+    return S.error;
+}
+
+// Blocks currently visible from camera pose P (row-major camera-to-world [R|t]) under the
+// scene's intrinsics and depth range: a block counts when its central voxel, local
+// (4, 4, 4), projects to a pixel inside the image at a camera depth that is a valid depth
+// measurement.  The projection takes the float32 steps of integration.  Keys in ascending
+// packed order; returns the count.
+int64_t orc_visible_blocks(void *s, const float *P, int32_t *keys, int64_t cap) {
+    const Scene &S = *static_cast<const Scene *>(s);
+    const orc_params &p = S.p;
+    std::vector<uint64_t> vis;
+    for (uint64_t key : S.block_key) {
+        int32_t Bk[3];
+        unpack(key, Bk);
+        float dl[3];
+        for (int i = 0; i < 3; ++i) dl[i] = float(int64_t(Bk[i]) * 8 + 4) * p.voxel_size - P[i * 4 + 3];
+        float pc[3];
+        for (int j = 0; j < 3; ++j) pc[j] = (P[0 * 4 + j] * dl[0] + P[1 * 4 + j] * dl[1]) + P[2 * 4 + j] * dl[2];
+        if (!(pc[2] > 0.0f) || !depth_valid(pc[2], p)) continue;
+        const float fu = std::floor((p.fx * (pc[0] / pc[2]) + p.cx) + 0.5f);
+        const float fv = std::floor((p.fy * (pc[1] / pc[2]) + p.cy) + 0.5f);
+        if (fu >= 0.0f && fu < float(p.width) && fv >= 0.0f && fv < float(p.height)) vis.push_back(key);
+    }
+    std::sort(vis.begin(), vis.end());
+    return write_keys(vis, keys, cap);
+}
+
 int orc_extract_mc(void *s, const int32_t *keys, int64_t n, uint8_t *mc, uint8_t *rgb) {
     Scene &S = *static_cast<Scene *>(s);
 #pragma omp parallel for schedule(dynamic, 16)

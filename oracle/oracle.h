@@ -72,6 +72,13 @@ int orc_read_blocks(void *s, const int32_t *keys, int64_t n, double *F, uint8_t 
  * blocks and their seven negative neighbours, stamped and logged as frame_id. */
 int orc_write_blocks(void *s, const int32_t *keys, int64_t n, const float *F, const uint8_t *W,
                      const uint8_t *rgb, uint32_t frame_id);
+/* Scene reset (Sec. 4.1): listed blocks that exist get F = 0, W = 0, colour 0; the MC
+ * voxels of those blocks and their seven negative neighbours are recomputed and logged as
+ * frame_id.  Absent keys are skipped.  *n_reset (may be NULL) = distinct blocks reset. */
+int orc_reset_blocks(void *s, const int32_t *keys, int64_t n, uint32_t frame_id, int64_t *n_reset);
+/* Blocks whose central voxel (local 4,4,4) projects into the image at a valid depth under
+ * pose P (camera-to-world 3x4); ascending packed-key order, up to cap; returns the count. */
+int64_t orc_visible_blocks(void *s, const float *P, int32_t *keys, int64_t cap);
 /* MC voxels recomputed from the current TSDF: mc [n*512], rgb [n*512*3] (may be NULL). */
 int orc_extract_mc(void *s, const int32_t *keys, int64_t n, uint8_t *mc, uint8_t *rgb);
 /* MC voxels as stored by the last update of each block (zeros for absent blocks). */
