@@ -227,6 +227,26 @@ int vbh_scene_read_blocks(vbh_scene *s, const int32_t *d_keys, int64_t n, float 
 int vbh_scene_write_blocks(vbh_scene *s, const int32_t *d_keys, int64_t n, const float *d_F, const uint8_t *d_W,
                            const uint8_t *d_rgb, uint32_t frame_id, void *stream);
 
+/* Scene reset (Sec. 4.1, quasi-static scenes: the parts of the model that are currently
+ * visible are deleted and the list of their blocks goes to the server, so that the region
+ * can be reconstructed anew).  Each of the n keys (duplicates allowed) whose block exists
+ * loses its reconstruction: F = 0, W = 0 and colour 0 for all 512 voxels, so the block
+ * reads as never observed.  The MC voxels of the reset blocks and of their seven negative
+ * neighbours are then recomputed and logged as update frame_id (same rules as
+ * vbh_integrate_frame), which delivers the now-empty blocks to every client.  Keys whose
+ * block does not exist are skipped; nothing is allocated and blocks keep their pool
+ * storage.  The reset blocks are the update's touched set (vbh_scene_last_touched).
+ * frame_id must exceed every earlier update's id; keys out of range record VBH_EINVAL. */
+int vbh_scene_reset_blocks(vbh_scene *s, const int32_t *d_keys, int64_t n, uint32_t frame_id, void *stream);
+/* Synchronising: the blocks currently visible from pose_c2w (host float[12], row-major
+ * camera-to-world) under the scene's intrinsics and depth range - those whose central
+ * voxel, local (4, 4, 4), projects to a pixel inside the image at a camera depth in
+ * [depth_min, depth_max] (the projection of integration).  Writes up to cap keys, in no
+ * particular order, to d_keys int32 [cap][3]; *h_count = number of visible blocks (may
+ * exceed cap).  The input of vbh_scene_reset_blocks for the reset of Sec. 4.1. */
+int vbh_scene_visible_blocks(vbh_scene *s, const float *pose_c2w, int32_t *d_keys, int64_t cap, int64_t *h_count,
+                             void *stream);
+
 /* Synchronising check, then enqueues a copy of log entries [start, start + n) (which must
  * lie below the log length): d_frame uint32 [n] update frame ids, d_keys int32 [n][3]
  * block keys (either may be NULL).  The log is append-only, so it is the full history of

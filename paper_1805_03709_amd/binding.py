@@ -106,6 +106,8 @@ SIGNATURES = {
     "vbh_scene_enable_timing": ([_V, _I32], C.c_int),
     "vbh_scene_timing": ([_V, C.POINTER(C.c_double), C.POINTER(_I64), _V], C.c_int),
     "vbh_scene_log_entries": ([_V, _U64, _I64, _P, _P, _V], C.c_int),
+    "vbh_scene_reset_blocks": ([_V, _P, _I64, C.c_uint32, _V], C.c_int),
+    "vbh_scene_visible_blocks": ([_V, C.POINTER(C.c_float), _P, _I64, C.POINTER(_I64), _V], C.c_int),
     "vbh_server_create": ([_V, C.POINTER(vbh_server_config), C.POINTER(_V)], C.c_int),
     "vbh_server_destroy": ([_V], None),
     "vbh_server_set_cursor": ([_V, _I32, _U64], C.c_int),
@@ -388,6 +390,21 @@ class Scene:
         _check(lib().vbh_scene_read_blocks(self.h, kp, n, _ptr(F), _ptr(W), _ptr(rgb), _ptr(found), _stream()),
                "vbh_scene_read_blocks")
         return F, W, rgb, found
+
+    def vbh_scene_reset_blocks(self, keys, frame_id: int):
+        kp, n = _keys(keys)
+        _check(lib().vbh_scene_reset_blocks(self.h, kp, n, frame_id, _stream()), "vbh_scene_reset_blocks")
+
+    def vbh_scene_visible_blocks(self, pose_c2w, device="cuda"):
+        P = _poses_f32(pose_c2w, 1)
+        pose = P.ctypes.data_as(C.POINTER(C.c_float))
+        cnt = C.c_int64()
+        _check(lib().vbh_scene_visible_blocks(self.h, pose, None, 0, C.byref(cnt), _stream()),
+               "vbh_scene_visible_blocks")
+        keys = torch.empty((max(cnt.value, 1), 3), dtype=torch.int32, device=device)
+        _check(lib().vbh_scene_visible_blocks(self.h, pose, _ptr(keys), cnt.value, C.byref(cnt), _stream()),
+               "vbh_scene_visible_blocks")
+        return keys[:cnt.value]
 
     def vbh_scene_log_entries(self, start: int, n: int, device="cuda"):
         fr = torch.empty(max(n, 1), dtype=torch.int32, device=device)

@@ -785,6 +785,89 @@ __global__ void __launch_bounds__(kBlock) k_load_copy(Dev S, const int32_t *keys
     }
 }
 
+// ------------------------------------------------------------------ scene reset
+// Reset (Sec. 4.1, quasi-static scenes): thread per listed key.  A key whose block exists
+// is stamped as touched by `frame` and appended to the update's touched list, from which
+// the MC update set (the block and its seven negative neighbours) is formed as for a
+// fused frame; absent keys are skipped and nothing is allocated.
+__global__ void __launch_bounds__(kBlock) k_reset_claim(Dev S, const int32_t *keys, int64_t n, uint32_t frame,
+                                                        int seq) {
+    FrameCounters *fc = &S.C->fc[seq & (kRing - 1)];
+    if (blockIdx.x == 0 && threadIdx.x == 0) begin_update(S, seq);
+    const int64_t stride = int64_t(gridDim.x) * kBlock;
+    for (int64_t b = int64_t(blockIdx.x) * kBlock + (threadIdx.x & ~63); b < n; b += stride) {
+        const int64_t i = b + lane_id();
+        bool append = false;
+        int64_t slot = -1;
+        if (i < n) {
+            const int32_t x = keys[3 * i], y = keys[3 * i + 1], z = keys[3 * i + 2];
+            if (!key_ok(x, y, z)) {
+                raise_err(&S.C->err, kErrKeyRange);
+            } else {
+                const uint64_t key = pack_key(x, y, z);
+                slot = probe_locate(S.T, S.mask, key, home_slot(x, y, z, key, S.kind, S.mask));
+                if (slot >= 0 && ld_val(S.T + slot) >= 0) append = atomicMax(&S.T[slot].stamp, frame) < frame;
+            }
+        }
+        const unsigned int pos = wave_append<unsigned int>(append, &fc->n_touched);
+        if (append) touched_of(S, seq)[pos] = int32_t(slot);
+    }
+}
+
+// Wave per block of the update's touched list: distance, weight, colour and the sign /
+// observed columns become zero, so the block reads as never observed.
+__global__ void __launch_bounds__(kBlock) k_reset_clear(Dev S, int seq) {
+    const int64_t n = S.C->fc[seq & (kRing - 1)].n_touched;
+    const int32_t *touched = touched_of(S, seq);
+    const int lane = lane_id();
+    const int64_t gw = int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6);
+    const int64_t nw = int64_t(gridDim.x) * kWaves;
+    for (int64_t t = gw; t < n; t += nw) {
+        const int64_t pool = S.T[touched[t]].val;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            S.F[pool * 512 + lane + 64 * j] = 0.0f;
+            S.WRGB[pool * 512 + lane + 64 * j] = 0u;
+        }
+        S.SGN[pool * 64 + lane] = 0;
+    }
+}
+
+// Blocks whose central voxel, local (4, 4, 4), projects into the image at a valid depth
+// (the float32 steps of integration); compacted in no particular order.
+__global__ void __launch_bounds__(kBlock) k_visible(Dev S, Frame fr, int64_t cap, int32_t *out) {
+    const unsigned long long pn = S.C->pool_next;
+    const int64_t n = int64_t(pn) < S.pool_cap ? int64_t(pn) : S.pool_cap;
+    const int64_t stride = int64_t(gridDim.x) * kBlock;
+    for (int64_t b = int64_t(blockIdx.x) * kBlock + (threadIdx.x & ~63); b < n; b += stride) {
+        const int64_t i = b + lane_id();
+        bool vis = false;
+        int32_t x = 0, y = 0, z = 0;
+        if (i < n) {
+            unpack_key(S.pool_key[i], x, y, z);
+            const float dlx = float(8 * x + 4) * fr.vs - fr.P[3];
+            const float dly = float(8 * y + 4) * fr.vs - fr.P[7];
+            const float dlz = float(8 * z + 4) * fr.vs - fr.P[11];
+            const float pcx = (fr.P[0] * dlx + fr.P[4] * dly) + fr.P[8] * dlz;
+            const float pcy = (fr.P[1] * dlx + fr.P[5] * dly) + fr.P[9] * dlz;
+            const float pcz = (fr.P[2] * dlx + fr.P[6] * dly) + fr.P[10] * dlz;
+            if (pcz > 0.0f && depth_valid(pcz, fr)) {
+                const float fu = floorf((fr.fx * (pcx / pcz) + fr.cx) + 0.5f);
+                const float fv = floorf((fr.fy * (pcy / pcz) + fr.cy) + 0.5f);
+                vis = fu >= 0.0f && fu < float(fr.W) && fv >= 0.0f && fv < float(fr.H);
+            }
+        }
+        const unsigned long long pos = wave_append<unsigned long long>(vis, &S.C->visible);
+        if (vis && int64_t(pos) < cap) {
+            out[3 * pos] = x;
+            out[3 * pos + 1] = y;
+            out[3 * pos + 2] = z;
+        }
+    }
+}
+
+__global__ void k_zero_visible(Counters *C) { C->visible = 0; }
+
 __global__ void __launch_bounds__(kBlock) k_keys_of(Dev S, int which, int seq, int64_t cap, int32_t *out) {
     // which: 0 = pool order (all blocks), 1 = last touched list, 2 = last MC list
     int64_t n;
@@ -1365,6 +1448,33 @@ int vbh_scene_write_blocks(vbh_scene *s, const int32_t *d_keys, int64_t n, const
     if (int rc = mc_update(s, frame_id, seq, st)) return rc;
     s->seq = seq + 1;
     s->last_frame = frame_id;
+    return VBH_OK;
+}
+
+int vbh_scene_reset_blocks(vbh_scene *s, const int32_t *d_keys, int64_t n, uint32_t frame_id, void *stream) {
+    if (!s || n < 0 || (n > 0 && !d_keys) || frame_id == 0 || frame_id <= s->last_frame) return VBH_EINVAL;
+    hipStream_t st = as_stream(stream);
+    const int seq = s->seq;
+    k_reset_claim<<<grid_for(n, kBlock, 8192), kBlock, 0, st>>>(s->d, d_keys, n, frame_id, seq);
+    k_reset_clear<<<wave_grid(s, n), kBlock, 0, st>>>(s->d, seq);
+    VBH_LAUNCHED();
+    if (int rc = mc_update(s, frame_id, seq, st)) return rc;
+    s->seq = seq + 1;
+    s->last_frame = frame_id;
+    return VBH_OK;
+}
+
+int vbh_scene_visible_blocks(vbh_scene *s, const float *pose_c2w, int32_t *d_keys, int64_t cap, int64_t *h_count,
+                             void *stream) {
+    if (!s || !pose_c2w || cap < 0 || (cap > 0 && !d_keys)) return VBH_EINVAL;
+    hipStream_t st = as_stream(stream);
+    k_zero_visible<<<1, 1, 0, st>>>(s->C);
+    k_visible<<<unsigned(s->cus) * 8, kBlock, 0, st>>>(s->d, make_frame(s, pose_c2w), cap, d_keys);
+    VBH_LAUNCHED();
+    unsigned long long h = 0;
+    VBH_HIP(hipMemcpyAsync(&h, &s->C->visible, sizeof(h), hipMemcpyDeviceToHost, st));
+    VBH_HIP(hipStreamSynchronize(st));
+    if (h_count) *h_count = int64_t(h);
     return VBH_OK;
 }
 

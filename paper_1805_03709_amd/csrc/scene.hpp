@@ -50,7 +50,9 @@ struct Counters {
     unsigned long long tot_mc;
     unsigned long long tot_voxel_updates;
     uint32_t err;
-    uint32_t pad[7];
+    uint32_t pad;
+    unsigned long long visible;  // result count of the last visible-block selection
+    uint32_t pad2[4];
 };
 
 // Device view of a scene, passed by value to kernels.
