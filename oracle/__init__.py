@@ -42,6 +42,7 @@ def lib():
             "orc_write_blocks": ([vp, i32p, i64, f32p, u8p, u8p, C.c_uint32], C.c_int),
             "orc_reset_blocks": ([vp, i32p, i64, C.c_uint32, C.c_void_p], C.c_int),
             "orc_visible_blocks": ([vp, f32p, i32p, i64], i64),
+            "orc_mc_triangles": ([i32p, C.c_void_p, i64, C.c_float, f32p, u8p, i64], i64),
             "orc_extract_mc": ([vp, i32p, i64, u8p, u8p], C.c_int),
             "orc_stored_mc": ([vp, i32p, i64, u8p, u8p], C.c_int),
             "orc_updated_since": ([vp, C.c_uint64, i64, i32p, C.c_void_p], i64),
@@ -311,3 +312,14 @@ def rel_err(g, g_ref, scale_ref=None):
     g, g_ref = np.asarray(g, np.float64), np.asarray(g_ref, np.float64)
     s = np.abs(g_ref).max() if scale_ref is None else scale_ref
     return np.abs(g - g_ref) / np.maximum(np.abs(g_ref), 1e-3 * s)
+
+
+def mc_triangles(keys, mcv, voxel_size):
+    """Client triangulation of MC voxel blocks: (pos float32 [m,3,3], rgb uint8 [m,3])."""
+    k, n = _keys(keys)
+    v = np.ascontiguousarray(mcv).view(np.uint32).reshape(n, 512)
+    m = lib().orc_mc_triangles(_p(k), v.ctypes.data, n, voxel_size, None, None, 0)
+    pos = np.empty((max(m, 1), 3, 3), np.float32)
+    rgb = np.empty((max(m, 1), 3), np.uint8)
+    lib().orc_mc_triangles(_p(k), v.ctypes.data, n, voxel_size, _p(pos), _p(rgb), m)
+    return pos[:m], rgb[:m]

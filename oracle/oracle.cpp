@@ -253,6 +253,86 @@ int64_t write_keys(const std::vector<uint64_t> &v, int32_t *keys, int64_t cap) {
 
 }  // namespace
 
+// Client geometry from MC voxels (Sec. 4.3; vertices without interpolation, Sec. 6).
+// Cube corners k = 0..7 at kCorner[k]; corner k is inside the surface iff bit k of the
+// case index is set (F < 0).  A vertex sits at the midpoint of every cube edge whose two
+// corners differ.  On each cube face the crossing points are joined in pairs: two
+// crossings by one segment; four (inside corners diagonal) by one segment around each
+// inside corner, which neighbouring cells sharing the face decide identically.  The
+// segments close into loops; each loop is oriented so that its normal points from the
+// inside corners to the outside ones, started at its lowest edge and cut into a fan.
+namespace mesh {
+const int kEdge[12][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 0}, {4, 5}, {5, 6},
+                          {6, 7}, {7, 4}, {0, 4}, {1, 5}, {2, 6}, {3, 7}};
+const int kFace[6][4] = {{0, 1, 2, 3}, {4, 5, 6, 7}, {0, 1, 5, 4}, {3, 2, 6, 7}, {0, 3, 7, 4}, {1, 2, 6, 5}};
+
+int edge_of(int a, int b) {
+    for (int e = 0; e < 12; ++e)
+        if ((kEdge[e][0] == a && kEdge[e][1] == b) || (kEdge[e][0] == b && kEdge[e][1] == a)) return e;
+    return -1;
+}
+
+// Triangles of one case as edge triples, in output order.
+std::vector<std::array<int, 3>> cell(uint32_t idx) {
+    auto in = [&](int k) { return ((idx >> k) & 1u) != 0; };
+    std::vector<int> nb[12];
+    for (const auto &f : kFace) {
+        int cross[4], nc = 0;
+        for (int i = 0; i < 4; ++i) {
+            const int a = f[i], b = f[(i + 1) & 3];
+            if (in(a) != in(b)) cross[nc++] = edge_of(a, b);
+        }
+        if (nc == 2) {
+            nb[cross[0]].push_back(cross[1]);
+            nb[cross[1]].push_back(cross[0]);
+        } else if (nc == 4) {
+            for (int i = 0; i < 4; ++i) {
+                if (!in(f[i])) continue;
+                const int e1 = edge_of(f[(i + 3) & 3], f[i]), e2 = edge_of(f[i], f[(i + 1) & 3]);
+                nb[e1].push_back(e2);
+                nb[e2].push_back(e1);
+            }
+        }
+    }
+    std::vector<std::array<int, 3>> tris;
+    bool used[12] = {};
+    for (int s = 0; s < 12; ++s) {
+        if (nb[s].empty() || used[s]) continue;
+        std::vector<int> loop{s};
+        used[s] = true;
+        int prev = s, cur = std::min(nb[s][0], nb[s][1]);
+        while (cur != s) {
+            loop.push_back(cur);
+            used[cur] = true;
+            const int nx = nb[cur][0] == prev ? nb[cur][1] : nb[cur][0];
+            prev = cur;
+            cur = nx;
+        }
+        // Newell normal of the midpoints (doubled coordinates) against inside -> outside
+        long nrm[3] = {0, 0, 0}, dir[3] = {0, 0, 0};
+        const size_t L = loop.size();
+        for (size_t i = 0; i < L; ++i) {
+            const int ea = loop[i], eb = loop[(i + 1) % L];
+            long pa[3], pb[3];
+            for (int c = 0; c < 3; ++c) {
+                pa[c] = kCorner[kEdge[ea][0]][c] + kCorner[kEdge[ea][1]][c];
+                pb[c] = kCorner[kEdge[eb][0]][c] + kCorner[kEdge[eb][1]][c];
+            }
+            nrm[0] += (pa[1] - pb[1]) * (pa[2] + pb[2]);
+            nrm[1] += (pa[2] - pb[2]) * (pa[0] + pb[0]);
+            nrm[2] += (pa[0] - pb[0]) * (pa[1] + pb[1]);
+            const int inside = in(kEdge[ea][0]) ? kEdge[ea][0] : kEdge[ea][1];
+            const int outside = kEdge[ea][0] + kEdge[ea][1] - inside;
+            for (int c = 0; c < 3; ++c) dir[c] += kCorner[outside][c] - kCorner[inside][c];
+        }
+        if (nrm[0] * dir[0] + nrm[1] * dir[1] + nrm[2] * dir[2] < 0) std::reverse(loop.begin(), loop.end());
+        std::rotate(loop.begin(), std::min_element(loop.begin(), loop.end()), loop.end());
+        for (size_t i = 1; i + 1 < L; ++i) tris.push_back({loop[0], loop[i], loop[i + 1]});
+    }
+    return tris;
+}
+}  // namespace mesh
+
 extern "C" {
 
 void *orc_map_new(void) { return new Map(); }
@@ -448,6 +528,36 @@ int64_t orc_visible_blocks(void *s, const float *P, int32_t *keys, int64_t cap) 
     }
     std::sort(vis.begin(), vis.end());
     return write_keys(vis, keys, cap);
+}
+
+int64_t orc_mc_triangles(const int32_t *keys, const uint32_t *mcv, int64_t n, float voxel_size, float *pos,
+                         uint8_t *rgb, int64_t cap) {
+    int64_t m = 0;
+    const float half = 0.5f * voxel_size;
+    for (int64_t b = 0; b < n; ++b) {
+        for (int l = 0; l < 512; ++l) {
+            const uint32_t v = mcv[b * 512 + l];
+            const uint32_t idx = v & 0xFFu;
+            if (idx == 0 || idx == 255) continue;
+            const int64_t g[3] = {int64_t(keys[3 * b]) * 8 + (l & 7), int64_t(keys[3 * b + 1]) * 8 + ((l >> 3) & 7),
+                                  int64_t(keys[3 * b + 2]) * 8 + (l >> 6)};
+            for (const auto &t : mesh::cell(idx)) {
+                if (m < cap) {
+                    for (int k = 0; k < 3; ++k) {
+                        const int e = t[size_t(k)];
+                        for (int c = 0; c < 3; ++c) {
+                            const int64_t h = 2 * g[c] + (kCorner[mesh::kEdge[e][0]][c] + kCorner[mesh::kEdge[e][1]][c]);
+                            pos[(m * 3 + k) * 3 + c] = float(h) * half;
+                        }
+                    }
+                    if (rgb)
+                        for (int c = 0; c < 3; ++c) rgb[m * 3 + c] = uint8_t(v >> (8 * (c + 1)));
+                }
+                ++m;
+            }
+        }
+    }
+    return m;
 }
 
 int orc_extract_mc(void *s, const int32_t *keys, int64_t n, uint8_t *mc, uint8_t *rgb) {

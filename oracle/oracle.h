@@ -79,6 +79,12 @@ int orc_reset_blocks(void *s, const int32_t *keys, int64_t n, uint32_t frame_id,
 /* Blocks whose central voxel (local 4,4,4) projects into the image at a valid depth under
  * pose P (camera-to-world 3x4); ascending packed-key order, up to cap; returns the count. */
 int64_t orc_visible_blocks(void *s, const float *P, int32_t *keys, int64_t cap);
+/* Client geometry (Sec. 4.3): triangles of n blocks of MC voxels (keys int32 [n][3], mcv
+ * uint32 [n][512] index | RGB << 8), vertices at the midpoints of crossing cube edges.
+ * pos float32 [cap][3][3] world positions, rgb uint8 [cap][3] the cell's colour; block,
+ * then cell (x fastest), then the cell's loops in order.  Returns the triangle count. */
+int64_t orc_mc_triangles(const int32_t *keys, const uint32_t *mcv, int64_t n, float voxel_size, float *pos,
+                         uint8_t *rgb, int64_t cap);
 /* MC voxels recomputed from the current TSDF: mc [n*512], rgb [n*512*3] (may be NULL). */
 int orc_extract_mc(void *s, const int32_t *keys, int64_t n, uint8_t *mc, uint8_t *rgb);
 /* MC voxels as stored by the last update of each block (zeros for absent blocks). */
