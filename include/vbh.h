@@ -247,6 +247,30 @@ int vbh_scene_reset_blocks(vbh_scene *s, const int32_t *d_keys, int64_t n, uint3
 int vbh_scene_visible_blocks(vbh_scene *s, const float *pose_c2w, int32_t *d_keys, int64_t cap, int64_t *h_count,
                              void *stream);
 
+/* =================================================================== client mesh
+ * Client geometry (Sec. 4.3): triangles from n blocks of MC voxels as a client receives
+ * them - d_keys int32 [n][3], d_mcv uint32 [n][512] (index | R<<8 | G<<16 | B<<24, local
+ * voxel x fastest; the cell of voxel g has its corner 0 at g).  Each vertex is the
+ * midpoint of a cube edge whose corners lie on different sides (the paper's MC voxels
+ * carry no interpolation weights): world position (2g + a + b) * (voxel_size / 2) for an
+ * edge from corner offset a to b.  Per case, crossing points are paired face by face (one
+ * segment around each inside corner on a face whose inside corners are diagonal, so
+ * neighbouring cells agree and closed surfaces give closed meshes), joined into loops
+ * oriented from inside (F < 0) to outside, and fanned from each loop's lowest edge.
+ * Indices 0 and 255 give nothing.  Triangles are ordered by block, cell and loop.
+ * Outputs: d_pos float32 [cap][3][3], d_rgb uint8 [cap][3] (the cell's colour; may be
+ * NULL).  d_work: caller-owned int64 workspace of vbh_mc_work_size(n) elements.
+ * Synchronising: *h_count = number of triangles (may exceed cap; then only the first cap
+ * are written). */
+int64_t vbh_mc_work_size(int64_t n);
+/* Host-only query of the rule above, for clients that triangulate on the CPU: returns the
+ * number of triangles of case `index` (0..255, else VBH_EINVAL) and, if h_edges is not
+ * NULL, writes their cube edges (Lorensen-Cline numbering, e0 = corners 0-1 ... e11 =
+ * corners 3-7) as int8 [15], unused entries -1. */
+int vbh_mc_case(int32_t index, int8_t *h_edges);
+int vbh_mc_triangulate(const int32_t *d_keys, const uint32_t *d_mcv, int64_t n, float voxel_size, float *d_pos,
+                       uint8_t *d_rgb, int64_t cap, int64_t *d_work, int64_t *h_count, void *stream);
+
 /* Synchronising check, then enqueues a copy of log entries [start, start + n) (which must
  * lie below the log length): d_frame uint32 [n] update frame ids, d_keys int32 [n][3]
  * block keys (either may be NULL).  The log is append-only, so it is the full history of

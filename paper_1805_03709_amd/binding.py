@@ -107,6 +107,9 @@ SIGNATURES = {
     "vbh_scene_timing": ([_V, C.POINTER(C.c_double), C.POINTER(_I64), _V], C.c_int),
     "vbh_scene_log_entries": ([_V, _U64, _I64, _P, _P, _V], C.c_int),
     "vbh_scene_reset_blocks": ([_V, _P, _I64, C.c_uint32, _V], C.c_int),
+    "vbh_mc_work_size": ([_I64], _I64),
+    "vbh_mc_case": ([_I32, C.c_void_p], C.c_int),
+    "vbh_mc_triangulate": ([_P, _P, _I64, C.c_float, _P, _P, _I64, _P, C.POINTER(_I64), _V], C.c_int),
     "vbh_scene_visible_blocks": ([_V, C.POINTER(C.c_float), _P, _I64, C.POINTER(_I64), _V], C.c_int),
     "vbh_server_create": ([_V, C.POINTER(vbh_server_config), C.POINTER(_V)], C.c_int),
     "vbh_server_destroy": ([_V], None),
@@ -275,6 +278,25 @@ class ChainedMap(Map):
         h = C.c_void_p()
         _check(lib().vbh_map_create_chained(buckets, excess, hash_kind, C.byref(h)), "vbh_map_create_chained")
         self.h, self.slots, self.excess = h, buckets, excess
+
+
+def vbh_mc_triangulate(keys, mcv, voxel_size: float):
+    """Client triangles of MC voxel blocks (keys int32 [n,3], mcv int32/uint32 [n,512] on
+    the device): (pos float32 [m,3,3], rgb uint8 [m,3])."""
+    kp, n = _keys(keys)
+    if mcv.dtype not in (torch.int32, torch.uint32) or mcv.numel() < 512 * n:
+        raise TypeError("mcv must be a 32-bit [n, 512] device tensor")
+    mp = _ptr(mcv, None, 512 * n, "mcv")
+    work = torch.empty(max(int(lib().vbh_mc_work_size(n)), 1), dtype=torch.int64, device=keys.device)
+    cnt = C.c_int64()
+    _check(lib().vbh_mc_triangulate(kp, mp, n, voxel_size, None, None, 0, _ptr(work), C.byref(cnt), _stream()),
+           "vbh_mc_triangulate")
+    m = cnt.value
+    pos = torch.empty((max(m, 1), 3, 3), dtype=torch.float32, device=keys.device)
+    rgb = torch.empty((max(m, 1), 3), dtype=torch.uint8, device=keys.device)
+    _check(lib().vbh_mc_triangulate(kp, mp, n, voxel_size, _ptr(pos), _ptr(rgb), m, _ptr(work), C.byref(cnt),
+                                    _stream()), "vbh_mc_triangulate")
+    return pos[:m], rgb[:m]
 
 
 def make_params(vol, cam, hash_kind: int = VBH_HASH_SPATIAL) -> vbh_params:
