@@ -6,8 +6,11 @@ integration, MC update-set marking and MC voxel extraction, update log) of the
 2^22 slots).  Frames are pre-staged in HBM; the timed region is K consecutive frames into
 a fresh volume.  Prints one JSON line on stdout (progress goes to stderr).
 
-Also reported (secondary fields): hash-map Mops/s on 2^24 keys / 2^25 slots with 1M-op
-mixed batches, and the oracle timed on a bounded sample of the same workload.
+Also reported (secondary fields): the rate with per-frame PCIe uploads; MC against TSDF
+packet bandwidth for 128-1024-block requests at 100 Hz; client triangulation and scene
+reset on the fused scene; hash-map Mops/s on 2^24 keys (open addressing in 2^25 slots,
+and the chained design in the same memory) with 1M-op mixed batches; the differentiable
+form; the serving loop; and the oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -271,6 +274,50 @@ def bandwidth_bench(vbh, depth, rgb, traj, n_frames=300, fps=30.0, rate=100.0, s
     return out
 
 
+def client_bench(vbh, S, pose, frame_id, reps=5):
+    """On the fused full-size scene: client triangulation of every block's MC voxels, then
+    a scene reset of the blocks visible from `pose` (selection, clearing and MC update)."""
+    import numpy as np
+    import torch
+    from datagen import configs
+    keys = S.vbh_scene_export_blocks()
+    mc, c3 = S.vbh_stored_mc(keys)
+    mcv = (mc.to(torch.int64) | c3[..., 0].to(torch.int64) << 8 | c3[..., 1].to(torch.int64) << 16
+           | c3[..., 2].to(torch.int64) << 24).to(torch.uint32).view(torch.int32).contiguous()
+    del mc, c3
+    vs = configs.FULL_VOL.voxel_size
+    pos, rgb = vbh.vbh_mc_triangulate(keys, mcv, vs)  # warm-up, and the output size
+    n, m = keys.shape[0], pos.shape[0]
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        pos, rgb = vbh.vbh_mc_triangulate(keys, mcv, vs)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ms = float(np.median(ts))
+    alg = n * (2048 + 12) + m * (36 + 3)
+    mesh = {"blocks": n, "triangles": m, "ms": ms, "mtri_per_s": m / ms / 1e3, "algorithmic_GBps": alg / ms / 1e6,
+            "note": "two calls' worth of work: count + scan, a host read of the total, then emission"}
+    del pos, rgb
+    t0 = time.perf_counter()
+    vis = S.vbh_scene_visible_blocks(pose)
+    t1 = time.perf_counter()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    S.vbh_scene_reset_blocks(vis, frame_id)
+    e1.record()
+    torch.cuda.synchronize()
+    st = S.vbh_scene_stats()
+    if S.vbh_scene_status() != 0:
+        raise RuntimeError("scene reported an error in the reset")
+    reset = {"visible_blocks": int(vis.shape[0]), "select_ms": (t1 - t0) * 1e3, "reset_ms": e0.elapsed_time(e1),
+             "mc_blocks_republished": st["n_mc"], "scene_blocks": n}
+    return {"mesh": mesh, "reset": reset}
+
+
 def diff_bench(vbh, reps=5):
     """Differentiable form on 16 frames of the 640x480 sequence (2 cm voxels, 8 cm
     truncation, 100k samples): forward and backward kernel time (torch events on the
@@ -391,6 +438,7 @@ def main():
     ap.add_argument("--no-diff", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-bandwidth", action="store_true")
+    ap.add_argument("--no-client", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--timing-period", type=int, default=4,
@@ -456,6 +504,10 @@ def main():
                   "mc_blocks_per_frame": stats["total_mc"] / K,
                   "voxel_updates_per_frame": stats["total_voxel_updates"] / K},
     }
+    if not args.no_client:
+        log("[bench] client triangulation and scene reset on the fused scene")
+        result["client"] = client_bench(vbh, S, traj[K - 1], K + 1)
+        log(f"[bench] client: {result['client']}")
     S.close()
     log("[bench] fusion with per-frame host-to-device upload")
     result["fusion_with_h2d"] = h2d_fusion(vbh, depth, rgb, traj, min(K, 500))

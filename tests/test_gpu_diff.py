@@ -91,6 +91,6 @@ def test_autograd_function_matches_abi():
     E2 = DiffFusion(vbh.make_params(VOL, cam), depth.shape[0])
     l2, _ = E2.vbh_diff_forward(d.detach(), poses, f, p)
     gD, gxi = E2.vbh_diff_backward(d.detach(), poses, f, p, torch.full((), 3.0, device="cuda"))
-    assert abs(float(loss) - float(l2)) <= 1e-6 * float(l2)
+    assert abs(float(loss.detach()) - float(l2)) <= 1e-6 * float(l2)
     assert torch.allclose(d.grad, gD, rtol=1e-5, atol=1e-9)
     assert torch.allclose(xi.grad, gxi, rtol=1e-5, atol=1e-9)
