@@ -14,7 +14,8 @@
 //
 // Launches: per-block triangle counts (wave per block), per-chunk exclusive scan (one
 // workgroup per 1024 blocks), a scan of the chunk totals (one workgroup), and the
-// emission (wave per block, triangles of a wave's cells placed by a wave prefix sum).
+// emission (wave per block, one 64-cell slice at a time, consecutive lanes writing
+// consecutive output words).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -259,41 +260,73 @@ __global__ void __launch_bounds__(kChunk) k_tri_scan_sums(int64_t *sums, int64_t
     if (threadIdx.x == 0) sums[nchunks] = carry;
 }
 
+// LDS written by one lane and read by another lane of the same wavefront: the wavefront
+// executes its LDS operations in order, so only the compiler must not move them across.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int kSlabTri = 64 * kMaxTri;  // triangles of one wavefront's 64 cells, at most
+
+// Wave per block, 64 cells (one z slice) at a time.  The slice's triangles are contiguous
+// in the output; each lane records in LDS which of its triangles it holds, then
+// consecutive lanes write consecutive words of the slice's output, each looking up the
+// lane (cell) its word belongs to, so every store is coalesced.
 __global__ void __launch_bounds__(kBlock) k_tri_emit(const int32_t *keys, const uint32_t *mcv, int64_t n,
                                                      const int64_t *off, const int64_t *sums, float half, float *pos,
                                                      uint8_t *rgb, int64_t cap) {
+    // the case table in LDS: every output word looks up its triangle's edge
+    __shared__ int8_t s_tri[256 * 3 * kMaxTri];
+    __shared__ uint8_t s_mid[12 * 3];
+    __shared__ uint8_t s_owner[kWaves][kSlabTri];  // lane holding each triangle of the slice
+    for (int i = threadIdx.x; i < 256 * 3 * kMaxTri; i += kBlock) s_tri[i] = (&c_tri[0][0])[i];
+    if (threadIdx.x < 36) s_mid[threadIdx.x] = (&c_edge_mid[0][0])[threadIdx.x];
+    __syncthreads();
     const int lane = lane_id();
     const int64_t gw = int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6);
     const int64_t nw = int64_t(gridDim.x) * kWaves;
-    const int lx = lane & 7, ly = lane >> 3;
     for (int64_t b = gw; b < n; b += nw) {
         int64_t base = sums[b / kChunk] + off[b];
-        const int64_t gx = 2 * (int64_t(keys[3 * b]) * 8 + lx);
-        const int64_t gy = 2 * (int64_t(keys[3 * b + 1]) * 8 + ly);
-        const int64_t gz0 = 2 * int64_t(keys[3 * b + 2]) * 8;
+        const int64_t kx2 = 16 * int64_t(keys[3 * b]), ky2 = 16 * int64_t(keys[3 * b + 1]);
+        const int64_t kz2 = 16 * int64_t(keys[3 * b + 2]);
         for (int j = 0; j < 8; ++j) {
             const uint32_t v = mcv[b * 512 + lane + 64 * j];
             const int idx = int(v & 0xFFu);
-            const int nt = c_ntri[idx];
             int total;
-            const int64_t first = base + wave_excl_scan(nt, total);
-            const int64_t gz = gz0 + 2 * j;
-            for (int t = 0; t < nt; ++t) {
-                const int64_t m = first + t;
-                if (m >= cap) break;
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    const int e = c_tri[idx][3 * t + k];
-                    pos[(m * 3 + k) * 3 + 0] = float(gx + c_edge_mid[e][0]) * half;
-                    pos[(m * 3 + k) * 3 + 1] = float(gy + c_edge_mid[e][1]) * half;
-                    pos[(m * 3 + k) * 3 + 2] = float(gz + c_edge_mid[e][2]) * half;
-                }
-                if (rgb) {
-                    rgb[m * 3 + 0] = uint8_t(v >> 8);
-                    rgb[m * 3 + 1] = uint8_t(v >> 16);
-                    rgb[m * 3 + 2] = uint8_t(v >> 24);
+            const int nt = c_ntri[idx];
+            const int lo = wave_excl_scan(nt, total);
+            if (total == 0) continue;
+            uint8_t *const own = s_owner[threadIdx.x >> 6];
+            for (int t = 0; t < nt; ++t) own[lo + t] = uint8_t(lane);
+            wave_lds_sync();
+            const int64_t room = cap - base;  // triangles of this slice that fit the output
+            const int keep = room >= total ? total : (room > 0 ? int(room) : 0);
+            float *const gp = pos + base * 9;
+            for (int q0 = 0; q0 < keep * 9; q0 += 64) {
+                const int q = q0 + lane;
+                const int qq = q < keep * 9 ? q : keep * 9 - 1;
+                const int t = qq / 9, comp = qq - 9 * (qq / 9);
+                const int L = own[t];
+                const int oidx = __shfl(idx, L), olo = __shfl(lo, L);
+                const int e = s_tri[oidx * 3 * kMaxTri + 3 * (t - olo) + comp / 3];
+                const int c = comp % 3;
+                const int64_t g2 = c == 0 ? kx2 + 2 * (L & 7) : (c == 1 ? ky2 + 2 * (L >> 3) : kz2 + 2 * j);
+                const float val = float(g2 + s_mid[3 * e + c]) * half;
+                if (q < keep * 9) gp[q] = val;
+            }
+            if (rgb) {
+                uint8_t *const gc = rgb + base * 3;
+                for (int q0 = 0; q0 < keep * 3; q0 += 64) {
+                    const int q = q0 + lane;
+                    const int qq = q < keep * 3 ? q : keep * 3 - 1;
+                    const int t = qq / 3;
+                    const uint32_t ov = __shfl(v, int(own[t]));
+                    if (q < keep * 3) gc[q] = uint8_t(ov >> (8 * (qq - 3 * t + 1)));
                 }
             }
+            wave_lds_sync();  // the slice's owners are read before the next slice writes them
             base += total;
         }
     }
