@@ -439,6 +439,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-bandwidth", action="store_true")
     ap.add_argument("--no-client", action="store_true")
+    ap.add_argument("--no-h2d", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--timing-period", type=int, default=4,
@@ -509,9 +510,10 @@ def main():
         result["client"] = client_bench(vbh, S, traj[K - 1], K + 1)
         log(f"[bench] client: {result['client']}")
     S.close()
-    log("[bench] fusion with per-frame host-to-device upload")
-    result["fusion_with_h2d"] = h2d_fusion(vbh, depth, rgb, traj, min(K, 500))
-    log(f"[bench] {result['fusion_with_h2d']}")
+    if not args.no_h2d:
+        log("[bench] fusion with per-frame host-to-device upload")
+        result["fusion_with_h2d"] = h2d_fusion(vbh, depth, rgb, traj, min(K, 500))
+        log(f"[bench] {result['fusion_with_h2d']}")
     if not args.no_bandwidth:
         log("[bench] streaming bandwidth (MC packets vs TSDF packets)")
         result["bandwidth"] = bandwidth_bench(vbh, depth, rgb, traj)
