@@ -304,7 +304,10 @@ int vbh_scene_timing(vbh_scene *s, double *ms_out, int64_t *h_frames, void *stre
  * times on another stream; a frame's MC update waits until the requests in flight have
  * completed and no request is launched while it runs, so every request is served against
  * one scene version (result identical to running it alone at that version).
- * While a server runs, the scene must not be used through other entry points. */
+ * While a server runs, the scene must not be used through other entry points.  Between
+ * runs it may be (frames fused, blocks written or reset): each run starts from the
+ * scene's state at its entry, so such updates must have completed by then (for example,
+ * the caller synchronised the stream it issued them on). */
 typedef struct vbh_server vbh_server;
 
 typedef struct vbh_server_config {

@@ -364,6 +364,10 @@ int vbh_server_run(vbh_server *v, const vbh_request *reqs, int64_t n_req, const 
         res[i].status = 1;  // pending
     }
     vbh_scene *sc = v->scene;
+    // The scene may have changed through its own entry points since the last run (frames,
+    // written or reset blocks): serve from its state now.
+    if (read_log_end(v, v->istream, &v->end_v) != VBH_OK) return VBH_EHIP;
+    v->version = sc->last_frame;
     const auto t0 = Clock::now();
     // --- gate between serving and the MC update of fused frames
     std::mutex mu;

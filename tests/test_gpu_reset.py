@@ -100,3 +100,36 @@ def test_reset_everything_equals_fresh_volume():
     ma, ca = A.vbh_extract_mc_indices(kb)
     mb, cb = B.vbh_extract_mc_indices(kb)
     assert torch.equal(ma, mb) and torch.equal(ca, cb)
+
+
+def test_reset_reaches_serving_clients():
+    """A client that streamed the scene before a reset receives, with its next requests
+    through the serving loop, exactly the reset's update set, and the reset blocks as
+    MC blocks with no surface (Sec. 4.1 reset propagated to the clients, Sec. 4.2)."""
+    vbh = require_gpu()
+    _, depth, rgb, poses = configs.tiny_inputs(8)
+    S = vbh.Scene(vbh.make_params(VOL, CAM))
+    for f in range(8):
+        S.vbh_integrate_frame(depth[f].cuda(), rgb[f].cuda(), poses[f], f + 1)
+    nb = S.vbh_scene_stats()["n_blocks"]
+    srv = vbh.Server(S, arena_bytes=128 << 20, max_inflight=8, n_streams=2, n_clients=2, max_batch=4)
+    lim = nb + 16
+    outs = [(torch.zeros((lim, 3), dtype=torch.int32, device="cuda"),
+             torch.zeros((lim, 512), dtype=torch.int32, device="cuda"))]
+    r0 = srv.vbh_server_run([0], [lim], [0.0], outs)
+    assert r0["status"][0] == 0 and r0["count"][0] == nb  # the client holds the whole model
+    vis = S.vbh_scene_visible_blocks(poses[3])
+    S.vbh_scene_reset_blocks(vis, 9)
+    assert S.vbh_scene_status() == 0
+    upd = keyset(S.vbh_scene_last_mc())
+    r1 = srv.vbh_server_run([0], [lim], [0.0], outs)
+    k = int(r1["count"][0])
+    got = outs[0][0][:k]
+    say(f"[reset serve] {vis.shape[0]} reset, {len(upd)} republished, {k} delivered")
+    assert r1["status"][0] == 0 and keyset(got) == upd and k == len(upd)
+    reset = keyset(vis)
+    is_reset = torch.tensor([tuple(x) in reset for x in got.cpu().numpy().tolist()], device="cuda")
+    mcs = outs[0][1][:k]
+    assert not mcs[is_reset].any()  # no surface left in the reset blocks
+    if bool((~is_reset).any()):
+        assert mcs[~is_reset].any()  # refreshed neighbours keep their surface
