@@ -160,6 +160,14 @@ def test_chained_capacity_and_reuse():
     assert (m.vbh_find(to_dev(bad)).cpu().numpy() == ABSENT).all()
     m.vbh_map_status()
     assert m.vbh_map_size() == (0, 0)
+    # no excess entries at all: a key needs its bucket
+    z = vbh.ChainedMap(nb, 0, 0)
+    stz = z.vbh_insert(to_dev(keys), to_dev(np.arange(100, dtype=np.int32))).cpu().numpy()
+    assert (stz == 1).sum() == used and z.vbh_map_status() == vbh.binding.VBH_EFULL_TABLE
+    assert (z.vbh_erase(to_dev(keys[stz == 1])).cpu().numpy() == 1).all() and z.vbh_map_size() == (0, 0)
+    stz2 = z.vbh_insert(to_dev(keys[::-1].copy()), to_dev(np.arange(100, dtype=np.int32))).cpu().numpy()
+    assert (stz2 == 1).sum() == used
+    z.vbh_map_status()
     with pytest.raises(vbh.VbhError):
         vbh.ChainedMap(96, 16, 0)  # buckets not a power of two
     with pytest.raises(vbh.VbhError):
