@@ -70,7 +70,25 @@ def measured_traffic(kernel):
         return None
     d = t["per_dispatch"]["k_" + kernel]
     return {"fetch_bytes": d["fetch_MB"] * 1e6, "write_bytes": d["write_MB"] * 1e6,
-            "bytes": (d["fetch_MB"] + d["write_MB"]) * 1e6, "workload": t["workload"]}
+            "bytes": (d["fetch_MB"] + d["write_MB"]) * 1e6, "valu_insts": d.get("valu_insts"),
+            "workload": t["workload"]}
+
+
+# Vector-ALU issue peak: 256 CUs x 4 SIMDs x one wave64 instruction per 4 cycles x 2.4 GHz
+# (full-rate instructions), in wave64 VALU instructions per second.
+VALU_PEAK_WAVE_INSTR_S = 256 * 4 / 4 * 2.4e9
+
+
+def valu_issue(t, kernel_ms):
+    """The dominant kernel against the vector-ALU issue peak: measured VALU instructions per
+    launch (rocprofv3 SQ_INSTS_VALU, committed with the traffic counters) over the kernel
+    time measured in this run."""
+    if not t or not t.get("valu_insts") or kernel_ms <= 0:
+        return None
+    rate = t["valu_insts"] / (kernel_ms * 1e-3)
+    return {"valu_instructions_per_launch": t["valu_insts"], "achieved": rate / 1e9,
+            "peak": VALU_PEAK_WAVE_INSTR_S / 1e9, "unit": "G wave64 VALU instructions/s",
+            "frac": rate / VALU_PEAK_WAVE_INSTR_S}
 
 
 def run_fusion(vbh, depth, rgb, traj, K, W, period=4):
@@ -499,7 +517,8 @@ def main():
                      "traffic": (measured_traffic(dom) or {}).get("bytes"),
                      "traffic_detail": measured_traffic(dom),
                      "algorithmic_bytes_per_launch": bytes_frame[dom],
-                     "kernel_ms": ms_frame[dom], "timed_frames": frames},
+                     "kernel_ms": ms_frame[dom], "timed_frames": frames,
+                     "valu_issue": valu_issue(measured_traffic(dom), ms_frame[dom])},
         "stages": per_stage,
         "scene": {"blocks": stats["n_blocks"], "touched_per_frame": stats["total_touched"] / K,
                   "mc_blocks_per_frame": stats["total_mc"] / K,
