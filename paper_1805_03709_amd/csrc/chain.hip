@@ -159,7 +159,7 @@ __global__ void __launch_bounds__(kBatchBlock) k_chain_batch(ChainEntry *E, cons
                                                              const int32_t *vals, int64_t n, int32_t *out,
                                                              uint32_t *err) {
     constexpr bool kUpdates = OPC != 1;
-    __shared__ unsigned long long s_pop, s_rx, s_rb;
+    __shared__ unsigned long long s_cnt[3];  // this iteration's pops, list and bucket retirements
     const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (!kUpdates && t >= n) return;
     const bool in = t < n;
@@ -181,7 +181,7 @@ __global__ void __launch_bounds__(kBatchBlock) k_chain_batch(ChainEntry *E, cons
     const unsigned long long top = ctl->top;  // fixed while the batch runs
     uint32_t tries = 0;
     if (kUpdates) {
-        if (threadIdx.x == 0) s_pop = s_rx = s_rb = 0;
+        if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
         __syncthreads();
     }
     while (kUpdates ? __syncthreads_or(active) != 0 : __ballot(active) != 0) {
@@ -269,23 +269,23 @@ __global__ void __launch_bounds__(kBatchBlock) k_chain_batch(ChainEntry *E, cons
             const unsigned long long mp = __ballot(need_entry), mx = __ballot(ret_x), mb = __ballot(ret_b);
             unsigned long long wp = 0, wx = 0, wb = 0;
             if (lane_id() == 0) {
-                if (mp) wp = atomicAdd(&s_pop, (unsigned long long)__popcll(mp));
-                if (mx) wx = atomicAdd(&s_rx, (unsigned long long)__popcll(mx));
-                if (mb) wb = atomicAdd(&s_rb, (unsigned long long)__popcll(mb));
+                if (mp) wp = atomicAdd(&s_cnt[0], (unsigned long long)__popcll(mp));
+                if (mx) wx = atomicAdd(&s_cnt[1], (unsigned long long)__popcll(mx));
+                if (mb) wb = atomicAdd(&s_cnt[2], (unsigned long long)__popcll(mb));
             }
             __syncthreads();
-            if (threadIdx.x == 0) {
-                const unsigned long long np = s_pop, nx_ = s_rx, nb_ = s_rb;
-                s_pop = np ? atomicAdd(&ctl->used, np) : 0;
-                s_rx = nx_ ? atomicAdd(&ctl->retired_x, nx_) : 0;
-                s_rb = nb_ ? atomicAdd(&ctl->retired_b, nb_) : 0;
+            // three lanes claim the three global ranges at once (used, retired_x, retired_b
+            // are consecutive words of the control block)
+            if (threadIdx.x < 3) {
+                const unsigned long long c = s_cnt[threadIdx.x];
+                s_cnt[threadIdx.x] = c ? atomicAdd(&ctl->used + threadIdx.x, c) : 0ull;
             }
             __syncthreads();
-            const unsigned long long slot = s_pop + __shfl(wp, 0) + (unsigned long long)lanes_below(mp);
-            const unsigned long long rx = s_rx + __shfl(wx, 0) + (unsigned long long)lanes_below(mx);
-            const unsigned long long rb = s_rb + __shfl(wb, 0) + (unsigned long long)lanes_below(mb);
+            const unsigned long long slot = s_cnt[0] + __shfl(wp, 0) + (unsigned long long)lanes_below(mp);
+            const unsigned long long rx = s_cnt[1] + __shfl(wx, 0) + (unsigned long long)lanes_below(mx);
+            const unsigned long long rb = s_cnt[2] + __shfl(wb, 0) + (unsigned long long)lanes_below(mb);
             __syncthreads();
-            if (threadIdx.x == 0) s_pop = s_rx = s_rb = 0;  // next adds follow the loop's barrier
+            if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;  // next adds follow the loop's barrier
             if (need_entry) {
                 if (slot < top) {
                     const uint64_t e = stack[top - 1 - slot];

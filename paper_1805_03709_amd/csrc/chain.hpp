@@ -3,6 +3,7 @@
 // C ABI in map.hip.  The device protocol is described in chain.hip.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 namespace vbh {
@@ -21,6 +22,10 @@ struct ChainCtl {
     unsigned long long retired_x;  // list entries emptied by the running batch (log from the front)
     unsigned long long retired_b;  // buckets emptied by the running batch (log from the back)
 };
+
+static_assert(offsetof(ChainCtl, retired_x) == offsetof(ChainCtl, used) + 8 &&
+                  offsetof(ChainCtl, retired_b) == offsetof(ChainCtl, used) + 16,
+              "the batch kernel claims the three counters as consecutive words");
 
 struct ChainMap {
     ChainEntry *E = nullptr;  // [nb buckets][nx excess entries]
