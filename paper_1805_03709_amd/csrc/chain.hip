@@ -110,13 +110,14 @@ __device__ __forceinline__ Walk walk(const ChainEntry *E, uint64_t bucket, uint6
     w.broken = false;
     uint64_t i = bucket, prev_b = 0;
     int64_t prev = -1;
+    // Both words of an entry are requested together (one trip per entry); the lifetime
+    // check below accepts them in either order of arrival.
     w.bucket_b = ld_b(E, bucket);
-    uint64_t b = w.bucket_b;
+    uint64_t b = w.bucket_b, a = ld_a(E, bucket);
     // A link only ever points at an entry linked after the one holding it, so a walk
     // visits each entry at most once.
     for (uint64_t s = 0; s < total; ++s) {
         if (b & kOcc) {
-            const uint64_t a = ld_a(E, i);
             if (life_a(a) != life_b(b)) {
                 w.again = true;
                 return w;
@@ -140,6 +141,7 @@ __device__ __forceinline__ Walk walk(const ChainEntry *E, uint64_t bucket, uint6
         prev_b = b;
         i = n;
         b = ld_b(E, i);
+        a = ld_a(E, i);
     }
     raise_err(err, kErrSpin);
     w.broken = true;
