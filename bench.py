@@ -481,7 +481,7 @@ def main():
     ap.add_argument("--no-per-frame", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--timing-period", type=int, default=4,
+    ap.add_argument("--timing-period", type=int, default=16,
                     help="attach kernel start/stop events to every n-th frame of the timed run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (scale reference for HBM counters)")
