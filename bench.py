@@ -487,8 +487,8 @@ def main():
                     help="also run a plain 1 GiB device copy (scale reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported, this build runs "
-              "the path on a single GPU only", file=sys.stderr)
+        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported; the path runs on a "
+              "single GPU only", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_1805_03709_amd as vbh
