@@ -203,9 +203,15 @@ uint32_t mc_voxel(const Scene &S, uint64_t key, int l) {
         if (b->F[lc] < 0.0) idx |= 1u << k;
     }
     if (idx == 0 || idx == 255) return 0;
-    const Blk *self = S.get(key);
-    return idx | uint32_t(self->C[l * 3 + 0]) << 8 | uint32_t(self->C[l * 3 + 1]) << 16 |
-           uint32_t(self->C[l * 3 + 2]) << 24;
+    // the colour is that of the cell's corner-0 voxel, i.e. of g itself (every corner's
+    // block was found above)
+    const int kc = 0;
+    const int64_t cc[3] = {g[0] + kCorner[kc][0], g[1] + kCorner[kc][1], g[2] + kCorner[kc][2]};
+    const int64_t ccb[3] = {fdiv8(cc[0]), fdiv8(cc[1]), fdiv8(cc[2])};
+    const Blk *cbk = S.get(pack(ccb[0], ccb[1], ccb[2]));
+    const int lcol = int(cc[0] - 8 * ccb[0]) + 8 * int(cc[1] - 8 * ccb[1]) + 64 * int(cc[2] - 8 * ccb[2]);
+    return idx | uint32_t(cbk->C[lcol * 3 + 0]) << 8 | uint32_t(cbk->C[lcol * 3 + 1]) << 16 |
+           uint32_t(cbk->C[lcol * 3 + 2]) << 24;
 }
 
 // MC update of the given blocks plus their seven negative-direction neighbours that
@@ -609,5 +615,115 @@ int64_t orc_updated_since(void *s, uint64_t cursor, int64_t cap, int32_t *keys, 
 
 uint64_t orc_log_length(void *s) { return uint64_t(static_cast<Scene *>(s)->log.size()); }
 int orc_scene_error(void *s) { return static_cast<Scene *>(s)->error; }
+
+}  // extern "C"
+
+// ------------------------------------------------ per-client stream sets (Sec. 4.2)
+// One set per client of the blocks whose newest MC update it has not been sent yet, with
+// that update's frame id.  Updates enter every set; requests take the oldest updates
+// first.
+namespace {
+struct Streams {
+    const Scene *S;
+    size_t seen = 0;  // update-log entries absorbed so far
+    std::vector<std::unordered_map<uint64_t, uint32_t>> set;  // per client: block -> frame
+
+    void fill_all(int32_t c) {
+        auto &m = set[size_t(c)];
+        m.clear();
+        for (size_t i = 0; i < S->blocks.size(); ++i) m[S->block_key[i]] = S->blocks[i].mc_stamp;
+    }
+    // the client's set ordered by (update frame, packed key)
+    std::vector<std::pair<uint32_t, uint64_t>> ordered(int32_t c) const {
+        std::vector<std::pair<uint32_t, uint64_t>> v;
+        for (const auto &kv : set[size_t(c)]) v.emplace_back(kv.second, kv.first);
+        std::sort(v.begin(), v.end());
+        return v;
+    }
+};
+
+bool client_ok(const Streams &T, int32_t c) { return c >= 0 && size_t(c) < T.set.size(); }
+}  // namespace
+
+extern "C" {
+
+void *orc_streams_new(void *scene, int32_t n_clients) {
+    if (!scene || n_clients <= 0) return nullptr;
+    Streams *T = new Streams();
+    T->S = static_cast<const Scene *>(scene);
+    T->set.resize(size_t(n_clients));
+    for (int32_t c = 0; c < n_clients; ++c) T->fill_all(c);
+    T->seen = T->S->log.size();
+    return T;
+}
+
+void orc_streams_free(void *st) { delete static_cast<Streams *>(st); }
+
+int64_t orc_streams_sync(void *st) {
+    Streams &T = *static_cast<Streams *>(st);
+    const auto &log = T.S->log;
+    const int64_t added = int64_t(log.size() - T.seen);
+    for (; T.seen < log.size(); ++T.seen) {
+        const auto &e = log[T.seen];
+        for (auto &m : T.set) m[e.second] = e.first;  // newest update of the block
+    }
+    return added;
+}
+
+int orc_streams_reconnect(void *st, int32_t client) {
+    Streams &T = *static_cast<Streams *>(st);
+    if (!client_ok(T, client)) return ORC_EINVAL;
+    T.fill_all(client);
+    return ORC_OK;
+}
+
+int64_t orc_streams_pending(void *st, int32_t client, int32_t *keys, uint32_t *frames, int64_t cap) {
+    const Streams &T = *static_cast<const Streams *>(st);
+    if (!client_ok(T, client)) return ORC_EINVAL;
+    const auto v = T.ordered(client);
+    const int64_t n = std::min<int64_t>(cap, int64_t(v.size()));
+    for (int64_t i = 0; i < n; ++i) {
+        if (keys) unpack(v[size_t(i)].second, keys + 3 * i);
+        if (frames) frames[i] = v[size_t(i)].first;
+    }
+    return int64_t(v.size());
+}
+
+int64_t orc_streams_serve(void *st, int32_t client, int64_t limit, int32_t *keys) {
+    Streams &T = *static_cast<Streams *>(st);
+    if (!client_ok(T, client) || limit < 0) return ORC_EINVAL;
+    const auto v = T.ordered(client);
+    const int64_t n = std::min<int64_t>(limit, int64_t(v.size()));
+    for (int64_t i = 0; i < n; ++i) {
+        if (keys) unpack(v[size_t(i)].second, keys + 3 * i);
+        T.set[size_t(client)].erase(v[size_t(i)].second);
+    }
+    return n;
+}
+
+int orc_streams_take(void *st, int32_t client, int64_t limit, const int32_t *keys, int64_t n) {
+    Streams &T = *static_cast<Streams *>(st);
+    if (!client_ok(T, client) || limit < 0 || n < 0 || (n > 0 && !keys)) return ORC_EINVAL;
+    auto &m = T.set[size_t(client)];
+    if (n != std::min<int64_t>(limit, int64_t(m.size()))) return ORC_SERVE_ECOUNT;
+    std::vector<uint64_t> sent(static_cast<size_t>(n));
+    uint32_t newest = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const int32_t *k = keys + 3 * i;
+        if (!key_in_range(k[0], k[1], k[2])) return ORC_SERVE_ENOTPENDING;
+        sent[size_t(i)] = pack(k[0], k[1], k[2]);
+        const auto it = m.find(sent[size_t(i)]);
+        if (it == m.end()) return ORC_SERVE_ENOTPENDING;
+        newest = std::max(newest, it->second);
+    }
+    std::vector<uint64_t> uniq = sent;
+    std::sort(uniq.begin(), uniq.end());
+    if (std::adjacent_find(uniq.begin(), uniq.end()) != uniq.end()) return ORC_SERVE_EDUP;
+    // every pending block of an update older than the newest one sent must be sent too
+    for (const auto &kv : m)
+        if (kv.second < newest && !std::binary_search(uniq.begin(), uniq.end(), kv.first)) return ORC_SERVE_EORDER;
+    for (uint64_t k : sent) m.erase(k);
+    return ORC_OK;
+}
 
 }  // extern "C"

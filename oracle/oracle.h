@@ -95,6 +95,39 @@ int64_t orc_updated_since(void *s, uint64_t cursor, int64_t cap, int32_t *keys, 
 uint64_t orc_log_length(void *s);
 int orc_scene_error(void *s);
 
+/* ---- Serving: per-client stream sets (Sec. 4.2; reconnection Sec. 4.2/4.3) ----
+ * Each client has a set of the blocks updated since they were last sent to it.  Every MC
+ * update inserts its update set into every client's set (a block already pending keeps
+ * one entry, carrying the newest update's frame id).  A request of size limit removes
+ * min(limit, |set|) blocks and sends them with their current MC voxels.  The paper takes
+ * a random subset; this build's reading sends the oldest updates first, leaving free only
+ * the order among blocks of the same update.  A (re)connecting client's set holds every
+ * block of the model.
+ * The streams follow a scene's update log: orc_streams_sync absorbs the entries appended
+ * since the previous call (the scene must outlive the streams). */
+#define ORC_SERVE_ECOUNT (-20)      /* answer size differs from min(limit, |set|) */
+#define ORC_SERVE_EDUP (-21)        /* a block sent twice in one answer */
+#define ORC_SERVE_ENOTPENDING (-22) /* a block sent that the client's set does not hold */
+#define ORC_SERVE_EORDER (-23)      /* an older update left pending while a newer one was sent */
+/* Every client starts connected: its set holds every block of the scene. */
+void *orc_streams_new(void *scene, int32_t n_clients);
+void orc_streams_free(void *st);
+/* Absorbs the update-log entries appended since the last sync; returns how many. */
+int64_t orc_streams_sync(void *st);
+/* The client's set becomes every block of the model (reconnection). */
+int orc_streams_reconnect(void *st, int32_t client);
+/* The client's set in (update frame, packed key) order, up to cap keys [cap][3] and
+ * frames [cap] (either may be NULL); returns its size. */
+int64_t orc_streams_pending(void *st, int32_t client, int32_t *keys, uint32_t *frames, int64_t cap);
+/* Plain serving: removes and writes the first min(limit, |set|) blocks in (update frame,
+ * packed key) order to keys [limit][3]; returns the count. */
+int64_t orc_streams_serve(void *st, int32_t client, int64_t limit, int32_t *keys);
+/* Checks an answer chosen elsewhere against the rule above: n == min(limit, |set|), no
+ * block twice, every block pending, and no pending block of an older update than some
+ * sent block left out.  If valid the blocks leave the set and 0 is returned; otherwise the
+ * set is unchanged and an ORC_SERVE_E* code is returned. */
+int orc_streams_take(void *st, int32_t client, int64_t limit, const int32_t *keys, int64_t n);
+
 /* ---- Differentiable form: frozen-branch FP64 forward and finite differences ----
  * Frames are integrated into a fresh volume (F64), the loss is the sum of squared
  * trilinear F at K back-projected samples.  See oracle/diff.cpp. */
