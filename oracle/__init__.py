@@ -304,21 +304,27 @@ class Streams:
 
 class DiffProblemStruct(C.Structure):
     _fields_ = [("p", OrcParams), ("n_frames", C.c_int32), ("depth", C.c_void_p), ("poses", C.c_void_p),
-                ("n_samples", C.c_int64), ("sample_frame", C.c_void_p), ("sample_pixel", C.c_void_p)]
+                ("n_samples", C.c_int64), ("sample_frame", C.c_void_p), ("sample_pixel", C.c_void_p),
+                ("xi_ref", C.c_void_p)]
 
 
 class Diff:
     """Frozen-branch float64 forward and gradient of L = sum_k F_tri(x_k)^2 (see diff.cpp)."""
 
-    def __init__(self, vol, cam, depth, poses, sample_frame, sample_pixel, L=None):
+    def __init__(self, vol, cam, depth, poses, sample_frame, sample_pixel, L=None, xi_ref=None):
+        """poses: base poses T0 [F,3,4]; xi_ref [F,6] (optional): the reference point
+        T_f = Exp(xi_ref_f) T0_f at which the branches freeze and the gradient is taken."""
         self.L = L or lib()
         self.depth = np.ascontiguousarray(depth, np.float32)
         self.poses = np.ascontiguousarray(np.asarray(poses, np.float64).reshape(-1, 3, 4), np.float32)
         self.sf = np.ascontiguousarray(sample_frame, np.int32)
         self.sp = np.ascontiguousarray(sample_pixel, np.int32)
         self.F, self.HW = self.depth.shape[0], cam.width * cam.height
+        self.xi_ref = (np.zeros((self.F, 6)) if xi_ref is None
+                       else np.ascontiguousarray(np.asarray(xi_ref, np.float64).reshape(self.F, 6)))
         prob = DiffProblemStruct(make_params(vol, cam), self.F, self.depth.ctypes.data, self.poses.ctypes.data,
-                                 self.sf.size, self.sf.ctypes.data, self.sp.ctypes.data)
+                                 self.sf.size, self.sf.ctypes.data, self.sp.ctypes.data,
+                                 None if xi_ref is None else self.xi_ref.ctypes.data)
         self.h = self.L.orc_diff_new(C.byref(prob))
         if not self.h:
             raise ValueError("invalid differentiable problem")
@@ -357,8 +363,8 @@ class Diff:
 
     def fd_pose(self, f, a, h=1e-4, points=5):
         def fn(t):
-            xi = np.zeros((self.F, 6))
-            xi[f, a] = t
+            xi = self.xi_ref.copy()
+            xi[f, a] += t
             return self.loss(xi=xi)
         return self._central(fn, h, points)
 
@@ -368,7 +374,7 @@ class Diff:
         return self._central(lambda t: self.loss(v, t), h, points)
 
     def fd_direction(self, v_depth, v_xi, h=1e-4, points=5):
-        return self._central(lambda t: self.loss(v_depth, t, t * v_xi), h, points)
+        return self._central(lambda t: self.loss(v_depth, t, self.xi_ref + t * v_xi), h, points)
 
 
 def rel_err(g, g_ref, scale_ref=None):

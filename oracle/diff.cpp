@@ -10,6 +10,8 @@
 // written operation order, from the unperturbed inputs.  Values are float64:
 //   F_v = (1/n_v) sum_{f observes v} tsdf_f(v),  tsdf = D_f[pix] - z_f(v) (or trunc if
 //   clamped), z_f(v) = r3_f . (X_v - t_f) with T_f = Exp(xi_f) T0_f (xi = (rho; phi));
+//   the reference point is xi_ref (zero by default), and its poses rounded to float32
+//   take the decisions;
 //   x_k = T_f (D_f[p_k] K^-1 [u, v, 1]);  F_tri = sum_c w_c(frac) F_c.
 #include <algorithm>
 #include <array>
@@ -102,7 +104,9 @@ struct Diff {
     orc_params p{};
     int F = 0;
     int m_band = 0;
-    std::vector<float> depth, poses;
+    std::vector<float> depth, poses;  // poses: the reference point's, float32 (decisions)
+    std::vector<float> base_pose;     // T0 as given
+    std::vector<double> xi_ref;       // [F*6], empty = zero
     std::vector<int32_t> sf, sp;
     std::unordered_map<uint64_t, int64_t> index;  // block key -> block id
     std::vector<uint64_t> keys;
@@ -159,15 +163,55 @@ void sample_cell(const Diff &d, int64_t k, int64_t *base) {
     }
 }
 
-Pose pose64(const Diff &d, int f, const double *xi) {
+Pose base64(const float *P) {
     Pose T0;
-    const float *P = d.P(f);
     for (int i = 0; i < 3; ++i) {
         for (int j = 0; j < 3; ++j) T0.R[i][j] = double(P[i * 4 + j]);
         T0.t[i] = double(P[i * 4 + 3]);
     }
-    if (!xi) return T0;
+    return T0;
+}
+
+// Pose of frame f at xi (NULL: the reference point), float64.
+Pose pose64(const Diff &d, int f, const double *xi) {
+    const Pose T0 = base64(&d.base_pose[size_t(f) * 12]);
+    if (!xi) {
+        if (d.xi_ref.empty()) return T0;
+        xi = d.xi_ref.data();
+    }
     return compose(se3_exp(xi + 6 * f), T0);
+}
+
+// SE(3) left Jacobian of xi = (rho; phi) from its defining series,
+// J_l = sum_n ad(xi)^n / (n+1)!,  ad(xi) = [[phi^, rho^], [0, phi^]] (6x6).
+void left_jacobian(const double *xi, double J[6][6]) {
+    double ad[6][6] = {}, term[6][6] = {}, nxt[6][6];
+    double ph[3][3], rh[3][3];
+    hat(xi + 3, ph);
+    hat(xi, rh);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            ad[i][j] = ph[i][j];
+            ad[i][j + 3] = rh[i][j];
+            ad[i + 3][j + 3] = ph[i][j];
+        }
+    for (int i = 0; i < 6; ++i) {
+        term[i][i] = 1.0;  // ad^0 / 1!
+        for (int j = 0; j < 6; ++j) J[i][j] = term[i][j];
+    }
+    for (int n = 1; n <= 40; ++n) {  // term_n = term_{n-1} ad / (n+1)
+        for (int i = 0; i < 6; ++i)
+            for (int j = 0; j < 6; ++j) {
+                double s = 0;
+                for (int k = 0; k < 6; ++k) s += term[i][k] * ad[k][j];
+                nxt[i][j] = s / double(n + 1);
+            }
+        for (int i = 0; i < 6; ++i)
+            for (int j = 0; j < 6; ++j) {
+                term[i][j] = nxt[i][j];
+                J[i][j] += term[i][j];
+            }
+    }
 }
 
 void voxel_world(const Diff &d, int64_t gv, double *X, int64_t *g) {
@@ -253,7 +297,18 @@ void *orc_diff_new(const orc_diff_problem *prob) {
     d->m_band = int(std::floor(d->p.trunc / d->p.voxel_size + 0.5f));
     const int64_t HW = int64_t(d->p.width) * d->p.height;
     d->depth.assign(prob->depth, prob->depth + HW * d->F);
-    d->poses.assign(prob->poses, prob->poses + 12 * d->F);
+    d->base_pose.assign(prob->poses, prob->poses + 12 * d->F);
+    d->poses = d->base_pose;
+    if (prob->xi_ref) {
+        d->xi_ref.assign(prob->xi_ref, prob->xi_ref + 6 * d->F);
+        for (int f = 0; f < d->F; ++f) {  // the reference poses, rounded to float32
+            const Pose T = pose64(*d, f, nullptr);
+            for (int i = 0; i < 3; ++i) {
+                for (int j = 0; j < 3; ++j) d->poses[size_t(f) * 12 + i * 4 + j] = float(T.R[i][j]);
+                d->poses[size_t(f) * 12 + i * 4 + 3] = float(T.t[i]);
+            }
+        }
+    }
     d->sf.assign(prob->sample_frame, prob->sample_frame + prob->n_samples);
     d->sp.assign(prob->sample_pixel, prob->sample_pixel + prob->n_samples);
     const orc_params &p = d->p;
@@ -399,6 +454,18 @@ int orc_diff_grad(void *h, double *gD, double *gxi) {
             g[3] += c * (X[1] * r3[2] - X[2] * r3[1]);
             g[4] += c * (X[2] * r3[0] - X[0] * r3[2]);
             g[5] += c * (X[0] * r3[1] - X[1] * r3[0]);
+        }
+    }
+    // dL/dxi = J_l(xi_ref)^T (left-perturbation gradient at the reference poses)
+    if (!d.xi_ref.empty()) {
+        for (int f = 0; f < d.F; ++f) {
+            double J[6][6], g[6];
+            left_jacobian(&d.xi_ref[size_t(f) * 6], J);
+            for (int j = 0; j < 6; ++j) {
+                g[j] = 0;
+                for (int i = 0; i < 6; ++i) g[j] += J[i][j] * gxi[6 * f + i];
+            }
+            for (int j = 0; j < 6; ++j) gxi[6 * f + j] = g[j];
         }
     }
     return ORC_OK;

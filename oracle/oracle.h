@@ -139,16 +139,21 @@ typedef struct orc_diff_problem {
     int64_t n_samples;
     const int32_t *sample_frame;  /* [K] */
     const int32_t *sample_pixel;  /* [K] v*W+u */
+    const double *xi_ref;    /* [F,6] or NULL: the reference point is T_f = Exp(xi_ref_f) T0_f */
 } orc_diff_problem;
 
 void *orc_diff_new(const orc_diff_problem *prob);
 void orc_diff_free(void *d);
-/* Loss at the frozen reference point with depth perturbed by (d_depth, scale) along a
- * full-size direction (may be NULL) and poses left-perturbed by xi [F,6] (rho;phi, may
- * be NULL).  Branches (pixel indices, skips, clamps, trilinear cells, masks) are those
- * of the unperturbed point. */
+/* The poses are T_f = Exp(xi_f) T0_f with T0 the problem's float32 poses.  The reference
+ * point is xi = xi_ref (0 if NULL); its poses, rounded to float32, take every discrete
+ * decision (band blocks, pixel indices, skips, clamps, trilinear cells, masks).
+ * Loss with depth perturbed by (d_depth, scale) along a full-size direction (may be
+ * NULL) at poses Exp(xi_f) T0_f (xi [F,6] rho;phi; NULL = the reference point), with the
+ * branches of the reference point. */
 double orc_diff_loss(void *d, const double *d_depth, double scale, const double *xi);
-/* Analytic FP64 gradient of the frozen loss: grad_depth [F*H*W], grad_xi [F*6]. */
+/* Analytic FP64 gradient of the frozen loss at the reference point: grad_depth [F*H*W],
+ * grad_xi [F*6] = dL/dxi (the left-perturbation gradient mapped through the transpose of
+ * the SE(3) left Jacobian of xi_ref). */
 int orc_diff_grad(void *d, double *grad_depth, double *grad_xi);
 /* Diagnostics: number of samples kept by the trilinear mask, number of voxels with
  * nonzero dL/dF, forward F at the samples [K] (NaN where masked). */

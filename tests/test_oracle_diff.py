@@ -104,3 +104,74 @@ def test_closed_form_two_planes(orc):
     assert np.abs(np.delete(gD.reshape(-1), [pix, 35 + pix])).max() < 1e-12
     assert abs(gxi[0, 2] + h) < 1e-12 and abs(gxi[1, 2] - h) < 1e-12
     assert np.abs(np.delete(gxi.reshape(-1), [2, 8])).max() < 1e-12
+
+
+XI_REF = np.array([[0.03, -0.02, 0.01, 0.05, -0.04, 0.08],
+                   [-0.02, 0.015, 0.03, -0.06, 0.02, 0.07],
+                   [0.01, 0.02, -0.025, 0.04, 0.09, -0.05]])
+
+
+def test_gradient_at_nonzero_xi_matches_fd(orc):
+    """At a nonzero reference xi (poses Exp(xi) T0, tens of mrad and cm), the analytic
+    gradient - the left-perturbation gradient mapped through J_l(xi)^T - equals 5-point
+    central differences of L(Exp(xi + h e) T0) in every pose coordinate and in sampled
+    depths; without the Jacobian the pose gradient is off by far more than the bar."""
+    cam, depth, poses, sf, sp = small_problem()
+    D = orc.Diff(VOL, cam, depth, poses, sf, sp, xi_ref=XI_REF)
+    assert D.info()["kept"] > 100
+    gD, gxi = D.grad()
+    fd = np.array([[D.fd_pose(f, a) for a in range(6)] for f in range(D.F)])
+    err = orc.rel_err(gxi, fd)
+    assert err.max() < 1e-4, (err.max(), gxi, fd)
+    rng = np.random.default_rng(3)
+    nz = np.argwhere(gD != 0)
+    pick = nz[rng.choice(len(nz), 24, replace=False)]
+    fdp = np.array([D.fd_depth(int(f), int(p)) for f, p in pick])
+    e = orc.rel_err(np.array([gD[f, p] for f, p in pick]), fdp, scale_ref=np.abs(gD).max())
+    assert e.max() < 1e-4
+    # the plain left-perturbation gradient at the same poses is a different vector
+    J = np.stack([left_jacobian_closed(XI_REF[f]) for f in range(D.F)])
+    g_left = np.linalg.solve(np.transpose(J, (0, 2, 1)), gxi[..., None])[..., 0]
+    assert orc.rel_err(g_left, fd).max() > 1e-2
+
+
+def left_jacobian_closed(xi):
+    """Closed form of the SE(3) left Jacobian, [[J, Q], [0, J]] (Barfoot and Furgale 2014),
+    written independently of the oracle's series; used to undo it above."""
+    rho, phi = xi[:3], xi[3:]
+    t = np.linalg.norm(phi)
+
+    def hat(w):
+        return np.array([[0, -w[2], w[1]], [w[2], 0, -w[0]], [-w[1], w[0], 0]])
+    P, R = hat(phi), hat(rho)
+    J = np.eye(3) + (1 - np.cos(t)) / t ** 2 * P + (t - np.sin(t)) / t ** 3 * P @ P
+    Q = (0.5 * R + (t - np.sin(t)) / t ** 3 * (P @ R + R @ P + P @ R @ P)
+         + (t ** 2 + 2 * np.cos(t) - 2) / (2 * t ** 4) * (P @ P @ R + R @ P @ P - 3 * P @ R @ P)
+         + (2 * t - 3 * np.sin(t) + t * np.cos(t)) / (2 * t ** 5) * (P @ R @ P @ P + P @ P @ R @ P))
+    out = np.zeros((6, 6))
+    out[:3, :3], out[:3, 3:], out[3:, 3:] = J, Q, J
+    return out
+
+
+def test_left_jacobian_closed_form_against_fd_of_exp(orc):
+    """The closed form used above satisfies Exp(xi + d) ~ Exp(J d) Exp(xi): checked by
+    central differences of the matrix exponential of the 4x4 twist (scipy's expm)."""
+    from scipy.linalg import expm, logm
+
+    def twist(x):
+        T = np.zeros((4, 4))
+        T[:3, :3] = np.array([[0, -x[5], x[4]], [x[5], 0, -x[3]], [-x[4], x[3], 0]])
+        T[:3, 3] = x[:3]
+        return T
+
+    for xi in XI_REF:
+        E = expm(twist(xi))
+        J = left_jacobian_closed(xi)
+        h = 1e-6
+        for a in range(6):
+            e = np.zeros(6)
+            e[a] = h
+            D = (expm(twist(xi + e)) - expm(twist(xi - e))) @ np.linalg.inv(E) / (2 * h)
+            v = np.array([D[0, 3], D[1, 3], D[2, 3], D[2, 1], D[0, 2], D[1, 0]])
+            assert np.abs(v - J[:, a]).max() < 1e-7
+        assert np.allclose(logm(E).real, twist(xi), atol=1e-12)
