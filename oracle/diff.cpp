@@ -10,8 +10,10 @@
 // written operation order, from the unperturbed inputs.  Values are float64:
 //   F_v = (1/n_v) sum_{f observes v} tsdf_f(v),  tsdf = D_f[pix] - z_f(v) (or trunc if
 //   clamped), z_f(v) = r3_f . (X_v - t_f) with T_f = Exp(xi_f) T0_f (xi = (rho; phi));
-//   the reference point is xi_ref (zero by default), and its poses rounded to float32
-//   take the decisions;
+//   the reference point is xi_ref (zero by default): its poses Exp(xi_ref) T0, rounded to
+//   float32 as the fusion's pose input, take the decisions and are the point where values
+//   and gradients are evaluated; a perturbed pose is Exp(xi) T0' with the float64 base
+//   T0' = Exp(-xi_ref) P32 that maps exactly onto that rounded reference pose P32;
 //   x_k = T_f (D_f[p_k] K^-1 [u, v, 1]);  F_tri = sum_c w_c(frac) F_c.
 #include <algorithm>
 #include <array>
@@ -105,7 +107,7 @@ struct Diff {
     int F = 0;
     int m_band = 0;
     std::vector<float> depth, poses;  // poses: the reference point's, float32 (decisions)
-    std::vector<float> base_pose;     // T0 as given
+    std::vector<Pose> base_T;         // T0' per frame (float64)
     std::vector<double> xi_ref;       // [F*6], empty = zero
     std::vector<int32_t> sf, sp;
     std::unordered_map<uint64_t, int64_t> index;  // block key -> block id
@@ -174,12 +176,8 @@ Pose base64(const float *P) {
 
 // Pose of frame f at xi (NULL: the reference point), float64.
 Pose pose64(const Diff &d, int f, const double *xi) {
-    const Pose T0 = base64(&d.base_pose[size_t(f) * 12]);
-    if (!xi) {
-        if (d.xi_ref.empty()) return T0;
-        xi = d.xi_ref.data();
-    }
-    return compose(se3_exp(xi + 6 * f), T0);
+    if (!xi) return base64(d.P(f));  // the reference pose (float32 values)
+    return compose(se3_exp(xi + 6 * f), d.base_T[size_t(f)]);
 }
 
 // SE(3) left Jacobian of xi = (rho; phi) from its defining series,
@@ -297,16 +295,22 @@ void *orc_diff_new(const orc_diff_problem *prob) {
     d->m_band = int(std::floor(d->p.trunc / d->p.voxel_size + 0.5f));
     const int64_t HW = int64_t(d->p.width) * d->p.height;
     d->depth.assign(prob->depth, prob->depth + HW * d->F);
-    d->base_pose.assign(prob->poses, prob->poses + 12 * d->F);
-    d->poses = d->base_pose;
+    d->poses.assign(prob->poses, prob->poses + 12 * d->F);
+    d->base_T.resize(size_t(d->F));
+    for (int f = 0; f < d->F; ++f) d->base_T[size_t(f)] = base64(d->P(f));
     if (prob->xi_ref) {
         d->xi_ref.assign(prob->xi_ref, prob->xi_ref + 6 * d->F);
-        for (int f = 0; f < d->F; ++f) {  // the reference poses, rounded to float32
-            const Pose T = pose64(*d, f, nullptr);
+        for (int f = 0; f < d->F; ++f) {
+            // the reference pose Exp(xi_ref) T0, rounded to float32 ...
+            const Pose T = compose(se3_exp(&d->xi_ref[size_t(f) * 6]), d->base_T[size_t(f)]);
             for (int i = 0; i < 3; ++i) {
                 for (int j = 0; j < 3; ++j) d->poses[size_t(f) * 12 + i * 4 + j] = float(T.R[i][j]);
                 d->poses[size_t(f) * 12 + i * 4 + 3] = float(T.t[i]);
             }
+            // ... and the base that Exp(xi_ref) maps onto it exactly
+            double neg[6];
+            for (int a = 0; a < 6; ++a) neg[a] = -d->xi_ref[size_t(f) * 6 + a];
+            d->base_T[size_t(f)] = compose(se3_exp(neg), base64(d->P(f)));
         }
     }
     d->sf.assign(prob->sample_frame, prob->sample_frame + prob->n_samples);

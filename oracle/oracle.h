@@ -145,10 +145,13 @@ typedef struct orc_diff_problem {
 void *orc_diff_new(const orc_diff_problem *prob);
 void orc_diff_free(void *d);
 /* The poses are T_f = Exp(xi_f) T0_f with T0 the problem's float32 poses.  The reference
- * point is xi = xi_ref (0 if NULL); its poses, rounded to float32, take every discrete
- * decision (band blocks, pixel indices, skips, clamps, trilinear cells, masks).
+ * point is xi = xi_ref (0 if NULL); its poses P32 = Exp(xi_ref) T0 rounded to float32 (the
+ * pose input of the fusion) take every discrete decision (band blocks, pixel indices,
+ * skips, clamps, trilinear cells, masks) and are where values and gradients are taken.
+ * A perturbed pose is Exp(xi) T0' with T0' = Exp(-xi_ref) P32 in float64, the base that
+ * maps exactly onto P32 (T0' = T0 when xi_ref is NULL).
  * Loss with depth perturbed by (d_depth, scale) along a full-size direction (may be
- * NULL) at poses Exp(xi_f) T0_f (xi [F,6] rho;phi; NULL = the reference point), with the
+ * NULL) at poses Exp(xi_f) T0'_f (xi [F,6] rho;phi; NULL = the reference point), with the
  * branches of the reference point. */
 double orc_diff_loss(void *d, const double *d_depth, double scale, const double *xi);
 /* Analytic FP64 gradient of the frozen loss at the reference point: grad_depth [F*H*W],
