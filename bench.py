@@ -112,12 +112,12 @@ def run_fusion(vbh, depth, rgb, traj, K, W, period=4):
     S.vbh_integrate_frames(depth[:K], rgb[:K], poses, 1)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    stage_ms, frames = S.vbh_scene_timing()
+    stage_ms, frames, timed_blocks = S.vbh_scene_timing(with_blocks=True)
     stats = S.vbh_scene_stats()
     status = S.vbh_scene_status()
     if status != 0:
         raise RuntimeError(f"scene reported error {status}")
-    return t1 - t0, stage_ms, frames, stats, S
+    return t1 - t0, stage_ms, frames, timed_blocks, stats, S
 
 
 def per_frame_calls(vbh, depth, rgb, traj, K):
@@ -461,7 +461,16 @@ def cpu_baseline(depth, rgb, traj, budget_s):
         if used >= budget_s:
             break
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": n / used, "unit": "frames/s", "cores": cores, "kind": "oracle",
+            "host": {"nproc": os.cpu_count(), "cpu_model": model, "omp_threads": cores},
             "sample": f"first {n} frames of the 640x480 sequence: allocation, integration and MC "
                       f"update into the same 5 mm volume ({used:.1f} s of oracle time)"}
 
@@ -481,8 +490,9 @@ def main():
     ap.add_argument("--no-per-frame", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--timing-period", type=int, default=16,
-                    help="attach kernel start/stop events to every n-th frame of the timed run")
+    ap.add_argument("--timing-period", type=int, default=0,
+                    help="attach kernel start/stop events to every n-th frame of the timed run "
+                         "(0: every frame up to 125 frames, then about 125 frames spread evenly)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (scale reference for HBM counters)")
     args = ap.parse_args()
@@ -508,17 +518,19 @@ def main():
         del src, dst
     depth, rgb, traj = stage_frames(max(K, W), "cuda")
     log("[bench] frames staged; fusing")
-    dt, stage_ms, frames, stats, S = run_fusion(vbh, depth, rgb, traj, K, W, args.timing_period)
+    period = args.timing_period or max(1, K // 125)
+    dt, stage_ms, frames, timed_blocks, stats, S = run_fusion(vbh, depth, rgb, traj, K, W, period)
     value = K / dt
     # kernel milliseconds per frame, averaged over the timed frames (every period-th frame)
     ms_frame = {s: v / max(frames, 1) for s, v in stage_ms.items()}
     log(f"[bench] {K} frames in {dt:.3f}s = {value:.1f} frames/s; kernel us/frame over {frames} timed frames: "
         + ", ".join(f"{s} {1e3 * v:.1f}" for s, v in ms_frame.items()))
-    # algorithmic bytes per frame (averaged over all K frames)
+    # algorithmic bytes per frame, from the blocks of exactly the timed frames
     hw = 640 * 480
+    nt = max(frames, 1)
     bytes_frame = {
-        "integrate": INT_BYTES_PER_BLOCK * stats["total_touched"] / K + INT_BYTES_PER_PIXEL * hw,
-        "mc_extract": MC_BYTES_PER_BLOCK * float(stats["total_mc"]) / K,
+        "integrate": INT_BYTES_PER_BLOCK * timed_blocks[0] / nt + INT_BYTES_PER_PIXEL * hw,
+        "mc_extract": MC_BYTES_PER_BLOCK * float(timed_blocks[1]) / nt,
     }
     dom = max(bytes_frame, key=lambda s: ms_frame[s])
     achieved = bytes_frame[dom] / (ms_frame[dom] * 1e-3) / 1e9
@@ -537,8 +549,14 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": (measured_traffic(dom) or {}).get("bytes"),
                      "traffic_detail": measured_traffic(dom),
+                     "traffic_source": "replayed from profiles/fusion_full_traffic.json (rocprofv3 "
+                                       "FETCH_SIZE + WRITE_SIZE per launch, scaled by a plain-copy "
+                                       "calibration, over the default 2000-frame run); not measured in "
+                                       "this run; null once the kernel source differs from the "
+                                       "profiled one",
                      "algorithmic_bytes_per_launch": bytes_frame[dom],
-                     "kernel_ms": ms_frame[dom], "timed_frames": frames,
+                     "timed_blocks_per_frame": {"touched": timed_blocks[0] / nt, "mc_set": timed_blocks[1] / nt},
+                     "kernel_ms": ms_frame[dom], "timed_frames": frames, "timing_period": period,
                      "valu_issue": valu_issue(measured_traffic(dom), ms_frame[dom])},
         "stages": per_stage,
         "scene": {"blocks": stats["n_blocks"], "touched_per_frame": stats["total_touched"] / K,

@@ -90,8 +90,16 @@ int vbh_map_create_chained(uint64_t buckets, uint64_t excess, int32_t hash_kind,
 void vbh_map_destroy(vbh_map *m);
 
 /* Insert-if-absent (Sec. 5, Insertion).  d_status[i] = 1 inserted, 0 already present
- * (the stored value is kept), VBH_EINVAL for a key out of range, VBH_EFULL_TABLE when
- * no slot was free.  d_vals must not contain VBH_ABSENT. */
+ * (the stored value is kept), VBH_EINVAL for a key out of range or a value equal to the
+ * reserved VBH_ABSENT (nothing is stored; vbh_map_status then reports VBH_EINVAL),
+ * VBH_EFULL_TABLE when no slot was free.
+ * Open addressing never reuses an erased slot within the table's life: erases leave
+ * tombstones, which keep occupying probe positions until vbh_map_rebuild (or
+ * vbh_map_clear).  Under sustained insert/erase traffic the caller watches the tombstone
+ * count of vbh_map_size and rebuilds before live + tombstones approach the slot count;
+ * an insert that finds no EMPTY slot on its probe sequence fails with VBH_EFULL_TABLE
+ * even if few keys are live.  No call rebuilds by itself (a rebuild allocates a second
+ * table). */
 int vbh_insert(vbh_map *m, const int32_t *d_keys, const int32_t *d_vals, int64_t n, int32_t *d_status,
                void *stream);
 /* Retrieval (Sec. 5): d_vals_out[i] = stored value or VBH_ABSENT. */
@@ -132,7 +140,7 @@ typedef struct vbh_params {
     int64_t log_capacity;  /* update-log entries, >= 1 */
     float voxel_size;      /* metres, > 0 */
     float trunc;           /* truncation band half-width mu, metres, >= voxel_size */
-    int32_t width, height; /* depth image size, > 0 */
+    int32_t width, height; /* depth image size, each in [1, 16384] */
     float fx, fy, cx, cy;  /* pinhole intrinsics in pixels */
     float depth_min;       /* valid depth range [depth_min, depth_max] */
     float depth_max;
@@ -283,11 +291,13 @@ int vbh_scene_log_entries(vbh_scene *s, uint64_t start, int64_t n, uint32_t *d_f
  * turns timing off (the default).  Stages: 0 band allocation with MC-set marking,
  * 1 integration, 2 stand-alone MC-set marking (not used by frame fusion, whose allocation
  * kernel forms the MC set), 3 MC extraction.  vbh_scene_timing synchronises the stream and returns,
- * per stage, the summed kernel milliseconds and the number of updates measured since the
- * last call (then resets).  ms_out must hold VBH_N_STAGES doubles.  EINVAL for period < 0. */
+ * per stage, the summed kernel milliseconds, the number of updates measured and (h_blocks,
+ * may be NULL) the touched blocks [0] and MC-set blocks [1] of exactly those updates, all
+ * since the last call (then resets).  ms_out must hold VBH_N_STAGES doubles.  EINVAL for
+ * period < 0. */
 #define VBH_N_STAGES 4
 int vbh_scene_enable_timing(vbh_scene *s, int32_t period);
-int vbh_scene_timing(vbh_scene *s, double *ms_out, int64_t *h_frames, void *stream);
+int vbh_scene_timing(vbh_scene *s, double *ms_out, int64_t *h_frames, int64_t *h_blocks, void *stream);
 
 /* ================================================================= serving loop
  * Streams MC voxel blocks to exploration clients (Sec. 4.2: per-client streaming state,
@@ -363,26 +373,35 @@ int vbh_server_run(vbh_server *srv, const vbh_request *reqs, int64_t n_req, cons
  *     L = sum_k F_tri(x_k)^2,
  * F_tri being the trilinear interpolation of F over the voxel lattice (voxel g at g *
  * voxel_size).  Samples whose 8 corner voxels are not all allocated and observed are
- * dropped (f_samples = NaN).  The backward pass returns dL/dD for every pixel and dL/dxi
- * for every frame, xi = (rho; phi) being a left perturbation T_f <- Exp(xi) T_f of the
- * camera-to-world pose; discrete decisions (allocation, pixel of each voxel, skip and
- * clamp branches, trilinear cells, the sample mask) are those of the forward point and
- * are not differentiated.  h_poses: host float32 [n_frames][12] (row-major 3x4). */
+ * dropped (f_samples = NaN).  The camera-to-world pose of frame f is
+ *     T_f = Exp(xi_f) T0_f,   xi_f = (rho; phi) in se(3),
+ * with T0_f the base pose (host float32 [n_frames][12], row-major 3x4) and xi a device
+ * float32 [n_frames][6] tangent vector (NULL = zero).  The library composes T_f in
+ * float64 and rounds it to the float32 pose that the fusion rules use.  The backward pass
+ * returns dL/dD for every pixel and dL/dxi_f = J_l(xi_f)^T g_f for every frame, where g_f
+ * is the gradient with respect to a left perturbation Exp(delta) T_f at delta = 0 and
+ * J_l the SE(3) left Jacobian; discrete decisions (allocation, pixel of each voxel, skip
+ * and clamp branches, trilinear cells, the sample mask) are those of the forward point
+ * and are not differentiated. */
 typedef struct vbh_diff vbh_diff;
 
 /* n_frames in [1, 32].  Owns a scene created with p. */
 int vbh_diff_create(const vbh_params *p, int32_t n_frames, vbh_diff **out);
 void vbh_diff_destroy(vbh_diff *d);
-/* d_f_samples: float32 [K] (may be NULL); d_loss: float32 scalar on the device. */
-int vbh_diff_forward(vbh_diff *d, const float *d_depth, const float *h_poses, const int32_t *d_sample_frame,
-                     const int32_t *d_sample_pixel, int64_t n_samples, float *d_f_samples, float *d_loss,
-                     void *stream);
-/* Must follow a forward with the same inputs.  d_grad_loss: device float32 scalar dL_out/dL;
- * outputs (overwritten): d_grad_depth float32 [n_frames][H][W], d_grad_xi float32
- * [n_frames][6]. */
-int vbh_diff_backward(vbh_diff *d, const float *d_depth, const float *h_poses, const int32_t *d_sample_frame,
-                      const int32_t *d_sample_pixel, int64_t n_samples, const float *d_grad_loss,
-                      float *d_grad_depth, float *d_grad_xi, void *stream);
+/* d_f_samples: float32 [K] (may be NULL); d_loss: float32 scalar on the device.  When
+ * d_xi is not NULL the call reads it back to the host and synchronises `stream` once
+ * (the composed poses are launch arguments); non-finite poses or xi give VBH_EINVAL. */
+int vbh_diff_forward(vbh_diff *d, const float *d_depth, const float *h_poses, const float *d_xi,
+                     const int32_t *d_sample_frame, const int32_t *d_sample_pixel, int64_t n_samples,
+                     float *d_f_samples, float *d_loss, void *stream);
+/* Must follow a forward with the same inputs: h_poses equal to the forward's base poses
+ * and d_xi NULL exactly when it was NULL there (else VBH_EINVAL); it reuses the forward's
+ * composed poses and reads d_xi on the device for J_l.  d_grad_loss: device float32
+ * scalar dL_out/dL; outputs (overwritten): d_grad_depth float32 [n_frames][H][W],
+ * d_grad_xi float32 [n_frames][6]. */
+int vbh_diff_backward(vbh_diff *d, const float *d_depth, const float *h_poses, const float *d_xi,
+                      const int32_t *d_sample_frame, const int32_t *d_sample_pixel, int64_t n_samples,
+                      const float *d_grad_loss, float *d_grad_depth, float *d_grad_xi, void *stream);
 
 #ifdef __cplusplus
 }

@@ -104,7 +104,7 @@ SIGNATURES = {
     "vbh_scene_read_blocks": ([_V, _P, _I64, _P, _P, _P, _P, _V], C.c_int),
     "vbh_scene_write_blocks": ([_V, _P, _I64, _P, _P, _P, C.c_uint32, _V], C.c_int),
     "vbh_scene_enable_timing": ([_V, _I32], C.c_int),
-    "vbh_scene_timing": ([_V, C.POINTER(C.c_double), C.POINTER(_I64), _V], C.c_int),
+    "vbh_scene_timing": ([_V, C.POINTER(C.c_double), C.POINTER(_I64), C.POINTER(_I64), _V], C.c_int),
     "vbh_scene_log_entries": ([_V, _U64, _I64, _P, _P, _V], C.c_int),
     "vbh_scene_reset_blocks": ([_V, _P, _I64, C.c_uint32, _V], C.c_int),
     "vbh_mc_work_size": ([_I64], _I64),
@@ -119,8 +119,8 @@ SIGNATURES = {
                         C.POINTER(vbh_request_result)], C.c_int),
     "vbh_diff_create": ([C.POINTER(vbh_params), _I32, C.POINTER(_V)], C.c_int),
     "vbh_diff_destroy": ([_V], None),
-    "vbh_diff_forward": ([_V, _P, C.POINTER(C.c_float), _P, _P, _I64, _P, _P, _V], C.c_int),
-    "vbh_diff_backward": ([_V, _P, C.POINTER(C.c_float), _P, _P, _I64, _P, _P, _P, _V], C.c_int),
+    "vbh_diff_forward": ([_V, _P, C.POINTER(C.c_float), _P, _P, _P, _I64, _P, _P, _V], C.c_int),
+    "vbh_diff_backward": ([_V, _P, C.POINTER(C.c_float), _P, _P, _P, _I64, _P, _P, _P, _V], C.c_int),
 }
 STAGES = ("alloc", "integrate", "mc_mark", "mc_extract")
 
@@ -439,11 +439,15 @@ class Scene:
         """Time the kernels of every `period`-th update (0 turns timing off)."""
         _check(lib().vbh_scene_enable_timing(self.h, int(period)), "vbh_scene_enable_timing")
 
-    def vbh_scene_timing(self):
-        """{stage: summed kernel ms}, frames measured (synchronising; resets)."""
+    def vbh_scene_timing(self, with_blocks=False):
+        """{stage: summed kernel ms}, frames measured (synchronising; resets); with_blocks
+        also returns (touched blocks, MC-set blocks) of exactly the measured updates."""
         ms = (C.c_double * len(STAGES))()
         frames = C.c_int64()
-        _check(lib().vbh_scene_timing(self.h, ms, C.byref(frames), _stream()), "vbh_scene_timing")
+        blk = (C.c_int64 * 2)()
+        _check(lib().vbh_scene_timing(self.h, ms, C.byref(frames), blk, _stream()), "vbh_scene_timing")
+        if with_blocks:
+            return dict(zip(STAGES, list(ms))), frames.value, (blk[0], blk[1])
         return dict(zip(STAGES, list(ms))), frames.value
 
     def vbh_scene_write_blocks(self, keys, F, W, rgb, frame_id: int):

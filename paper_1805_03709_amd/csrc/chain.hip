@@ -173,7 +173,8 @@ __global__ void __launch_bounds__(kBatchBlock) k_chain_batch(ChainEntry *E, cons
     if (in && op > 2) {
         raise_err(err, kErrKeyRange);
         active = false;
-    } else if (in && !key_ok(x, y, z)) {
+    } else if (in && (!key_ok(x, y, z) || (op == 0 && val == kAbsent))) {
+        // a key out of range, or an insert of the reserved value VBH_ABSENT
         raise_err(err, kErrKeyRange);
         res = op == 1 ? kAbsent : -1;
         active = false;

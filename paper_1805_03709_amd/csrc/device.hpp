@@ -139,7 +139,9 @@ __device__ __forceinline__ int64_t probe_locate(const Slot *T, uint64_t mask, ui
 // Returns the per-op result of the C ABI (status or value); errors set sticky bits.
 __device__ __forceinline__ int32_t map_op(Slot *T, uint64_t mask, int kind, int op, int32_t x, int32_t y, int32_t z,
                                           int32_t val, uint32_t *err) {
-    if (!key_ok(x, y, z)) {
+    if (!key_ok(x, y, z) || (op == 0 && val == kPending)) {
+        // a key out of range, or an insert of the reserved value (it marks a slot whose
+        // value is not yet published, and readers would wait on it)
         raise_err(err, kErrKeyRange);
         return op == 1 ? kAbsent : -1;
     }

@@ -2,8 +2,11 @@
 // fresh block-hashed volume (the band allocation kernel of scene.hip, then the voxel
 // means in float64 below),
 // the loss is L = sum_k F_tri(x_k)^2 over back-projected pixel samples, and the backward
-// pass gives dL/d(depth) per pixel and dL/d(xi) per frame for a left se(3) perturbation
-// T_f = Exp(xi_f) T_f of each camera-to-world pose, xi = (rho; phi).
+// pass gives dL/d(depth) per pixel and dL/d(xi) per frame, where each camera-to-world
+// pose is T_f = Exp(xi_f) T0_f with xi = (rho; phi) and T0_f the caller's base pose.  The
+// library composes T_f (float64, then rounded to the float32 pose the fusion kernels use),
+// accumulates the left-perturbation gradient g_f = dL/d(delta) of Exp(delta) T_f at
+// delta = 0, and returns dL/dxi_f = J_l(xi_f)^T g_f with J_l the SE(3) left Jacobian.
 //
 // Gradient (discrete decisions fixed at the forward point):
 //   samples:  dL/dF_c += 2 F_tri w_c;  g_x = 2 F_tri grad F_tri;
@@ -418,7 +421,7 @@ __global__ void __launch_bounds__(kBlock) k_integrate_bwd(DiffDev D, Frame fr, C
 
 // One workgroup per pose-gradient component i: a fixed-order sum of its per-workgroup
 // partials (rows), strided over the threads, then across the workgroup.
-__global__ void __launch_bounds__(kBlock) k_reduce_xi(DiffDev D, int n_part_a, int n_part_b, float *grad_xi) {
+__global__ void __launch_bounds__(kBlock) k_reduce_xi(DiffDev D, int n_part_a, int n_part_b, double *g_left) {
     // partials of k_sample_bwd occupy rows [0, n_part_a), those of k_integrate_bwd
     // rows [n_part_a, n_part_a + n_part_b) (written at an offset)
     __shared__ double part[kWaves];
@@ -432,7 +435,80 @@ __global__ void __launch_bounds__(kBlock) k_reduce_xi(DiffDev D, int n_part_a, i
     if (threadIdx.x == 0) {
         double t = 0.0;
         for (int w = 0; w < kWaves; ++w) t += part[w];
-        grad_xi[i] = float(t);
+        g_left[i] = t;
+    }
+}
+
+// 3x3 helpers in float64 for the pose Jacobian.
+__device__ __forceinline__ void hat3(const double *w, double M[3][3]) {
+    M[0][0] = 0.0;   M[0][1] = -w[2]; M[0][2] = w[1];
+    M[1][0] = w[2];  M[1][1] = 0.0;   M[1][2] = -w[0];
+    M[2][0] = -w[1]; M[2][1] = w[0];  M[2][2] = 0.0;
+}
+__device__ __forceinline__ void mul3(const double A[3][3], const double B[3][3], double C[3][3]) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) C[i][j] = A[i][0] * B[0][j] + A[i][1] * B[1][j] + A[i][2] * B[2][j];
+}
+
+// dL/dxi_f = J_l(xi_f)^T g_f.  J_l = [[J, Q], [0, J]] in (rho; phi) order, with J the SO(3)
+// left Jacobian of phi and Q the closed-form coupling block of the SE(3) left Jacobian
+// (Barfoot and Furgale, IEEE T-RO 2014); series coefficients below theta = 1e-2.
+// xi == nullptr: J_l = I.  One thread per frame.
+__global__ void k_pose_grad(const double *g_left, const float *xi, int F, float *grad_xi) {
+    const int f = threadIdx.x;
+    if (f >= F) return;
+    const double *g = g_left + 6 * f;
+    if (!xi) {
+        for (int i = 0; i < 6; ++i) grad_xi[6 * f + i] = float(g[i]);
+        return;
+    }
+    const double rho[3] = {xi[6 * f + 0], xi[6 * f + 1], xi[6 * f + 2]};
+    const double phi[3] = {xi[6 * f + 3], xi[6 * f + 4], xi[6 * f + 5]};
+    const double t2 = phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2];
+    const double t = sqrt(t2);
+    double a, b, c, d;  // (1-cos)/t^2, (t-sin)/t^3, (t^2+2cos-2)/(2t^4), (2t-3sin+t cos)/(2t^5)
+    if (t < 1e-2) {
+        a = 0.5 - t2 / 24.0 + t2 * t2 / 720.0;
+        b = 1.0 / 6.0 - t2 / 120.0 + t2 * t2 / 5040.0;
+        c = 1.0 / 24.0 - t2 / 720.0 + t2 * t2 / 40320.0;
+        d = 1.0 / 120.0 - t2 / 2520.0;
+    } else {
+        const double sn = sin(t), cs = cos(t);
+        a = (1.0 - cs) / t2;
+        b = (t - sn) / (t2 * t);
+        c = (t2 + 2.0 * cs - 2.0) / (2.0 * t2 * t2);
+        d = (2.0 * t - 3.0 * sn + t * cs) / (2.0 * t2 * t2 * t);
+    }
+    double P[3][3], R[3][3], PP[3][3], PR[3][3], RP[3][3], PRP[3][3], PPR[3][3], RPP[3][3], PRPP[3][3], PPRP[3][3];
+    hat3(phi, P);
+    hat3(rho, R);
+    mul3(P, P, PP);
+    mul3(P, R, PR);
+    mul3(R, P, RP);
+    mul3(PR, P, PRP);
+    mul3(PP, R, PPR);
+    mul3(R, PP, RPP);
+    mul3(PRP, P, PRPP);
+    mul3(PP, RP, PPRP);
+    double J[3][3], Q[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            J[i][j] = (i == j ? 1.0 : 0.0) + a * P[i][j] + b * PP[i][j];
+            Q[i][j] = 0.5 * R[i][j] + b * (PR[i][j] + RP[i][j] + PRP[i][j]) +
+                      c * (PPR[i][j] + RPP[i][j] - 3.0 * PRP[i][j]) + d * (PRPP[i][j] + PPRP[i][j]);
+        }
+    // [J Q; 0 J]^T g = (J^T g_rho ; Q^T g_rho + J^T g_phi)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const double top = J[0][j] * g[0] + J[1][j] * g[1] + J[2][j] * g[2];
+        const double bot = Q[0][j] * g[0] + Q[1][j] * g[1] + Q[2][j] * g[2] + J[0][j] * g[3] + J[1][j] * g[4] +
+                           J[2][j] * g[5];
+        grad_xi[6 * f + j] = float(top);
+        grad_xi[6 * f + 3 + j] = float(bot);
     }
 }
 
@@ -442,19 +518,52 @@ struct vbh_diff {
     vbh_scene *s = nullptr;
     int F = 0;
     DiffDev d{};
-    void *mem[7] = {};
+    void *mem[8] = {};
+    float *h_xi = nullptr;     // pinned staging of the caller's xi [F][6]
+    float base[kMaxFrames][12] = {};  // the forward's base poses T0
+    Cams cams{};               // the forward's composed poses Exp(xi) T0 (float32)
     bool have_forward = false;
+    bool with_xi = false;
 };
 
 namespace {
-int load_cams(const vbh_diff *D, const float *h_poses, Cams &cams) {
-    for (int f = 0; f < D->F; ++f) {
-        for (int i = 0; i < 12; ++i) {
-            if (!std::isfinite(h_poses[f * 12 + i])) return VBH_EINVAL;
-            cams.P[f][i] = h_poses[f * 12 + i];
-        }
+// Exp(xi) T0 in float64, rounded to float32.  Exp of xi = (rho; phi): rotation
+// R = I + (sin t / t) K + ((1 - cos t) / t^2) K^2 (Rodrigues, K = phi^, t = |phi|) and
+// translation V rho with V = I + ((1 - cos t) / t^2) K + ((t - sin t) / t^3) K^2.
+void compose_pose(const float *T0, const float *xi, float *P) {
+    const double rho[3] = {xi[0], xi[1], xi[2]}, phi[3] = {xi[3], xi[4], xi[5]};
+    const double t2 = phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2], t = std::sqrt(t2);
+    double A, B, Cc;
+    if (t < 1e-4) {
+        A = 1.0 - t2 / 6.0;
+        B = 0.5 - t2 / 24.0;
+        Cc = 1.0 / 6.0 - t2 / 120.0;
+    } else {
+        A = std::sin(t) / t;
+        B = (1.0 - std::cos(t)) / t2;
+        Cc = (t - std::sin(t)) / (t2 * t);
     }
-    return VBH_OK;
+    const double K[3][3] = {{0.0, -phi[2], phi[1]}, {phi[2], 0.0, -phi[0]}, {-phi[1], phi[0], 0.0}};
+    double R[3][3], V[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            const double K2 = K[i][0] * K[0][j] + K[i][1] * K[1][j] + K[i][2] * K[2][j];
+            R[i][j] = (i == j ? 1.0 : 0.0) + A * K[i][j] + B * K2;
+            V[i][j] = (i == j ? 1.0 : 0.0) + B * K[i][j] + Cc * K2;
+        }
+    for (int i = 0; i < 3; ++i) {
+        const double te = V[i][0] * rho[0] + V[i][1] * rho[1] + V[i][2] * rho[2];
+        for (int j = 0; j < 3; ++j)
+            P[i * 4 + j] = float(R[i][0] * double(T0[0 * 4 + j]) + R[i][1] * double(T0[1 * 4 + j]) +
+                                 R[i][2] * double(T0[2 * 4 + j]));
+        P[i * 4 + 3] = float(R[i][0] * double(T0[3]) + R[i][1] * double(T0[7]) + R[i][2] * double(T0[11]) + te);
+    }
+}
+
+bool finite_n(const float *p, int n) {
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
 }
 }  // namespace
 
@@ -473,12 +582,17 @@ int vbh_diff_create(const vbh_params *p, int32_t n_frames, vbh_diff **out) {
     const uint64_t P = uint64_t(p->pool_blocks);
     const size_t HW = size_t(p->width) * size_t(p->height);
     const size_t sizes[] = {P * 4, P * 512 * 8, P * 4, size_t(kMaxWG) * 8, size_t(2 * kMaxWG) * kMaxFrames * 6 * 8,
-                            HW * size_t(n_frames) * 8, P * 512 * 8};
-    for (int i = 0; i < 7; ++i) {
+                            HW * size_t(n_frames) * 8, P * 512 * 8, size_t(kMaxFrames) * 6 * 8};
+    for (int i = 0; i < 8; ++i) {
         if (hipMalloc(&D->mem[i], sizes[i]) != hipSuccess) {
             vbh_diff_destroy(D);
             return VBH_ENOMEM;
         }
+    }
+    if (hipHostMalloc(reinterpret_cast<void **>(&D->h_xi), size_t(kMaxFrames) * 6 * sizeof(float), 0) != hipSuccess) {
+        D->h_xi = nullptr;
+        vbh_diff_destroy(D);
+        return VBH_ENOMEM;
     }
     D->d.S = D->s->d;
     D->d.fmask = static_cast<uint32_t *>(D->mem[0]);
@@ -497,19 +611,36 @@ void vbh_diff_destroy(vbh_diff *D) {
     if (!D) return;
     for (void *m : D->mem)
         if (m) (void)hipFree(m);
+    if (D->h_xi) (void)hipHostFree(D->h_xi);
     vbh_scene_destroy(D->s);
     delete D;
 }
 
-int vbh_diff_forward(vbh_diff *D, const float *d_depth, const float *h_poses, const int32_t *d_sample_frame,
-                     const int32_t *d_sample_pixel, int64_t n_samples, float *d_f_samples, float *d_loss,
-                     void *stream) {
+int vbh_diff_forward(vbh_diff *D, const float *d_depth, const float *h_poses, const float *d_xi,
+                     const int32_t *d_sample_frame, const int32_t *d_sample_pixel, int64_t n_samples,
+                     float *d_f_samples, float *d_loss, void *stream) {
     if (!D || !d_depth || !h_poses || n_samples < 0 || (n_samples > 0 && (!d_sample_frame || !d_sample_pixel)) ||
-        !d_loss || (n_samples + kSampleWG - 1) / kSampleWG > kMaxWG)
+        !d_loss || (n_samples + kSampleWG - 1) / kSampleWG > kMaxWG || !finite_n(h_poses, 12 * D->F))
         return VBH_EINVAL;
     hipStream_t st = as_stream(stream);
-    Cams cams;
-    if (int rc = load_cams(D, h_poses, cams)) return rc;
+    D->have_forward = false;
+    if (d_xi) {
+        // the composed poses are kernel arguments: xi is read back once, synchronously
+        if (hipMemcpyAsync(D->h_xi, d_xi, size_t(D->F) * 6 * sizeof(float), hipMemcpyDeviceToHost, st) !=
+                hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return VBH_EHIP;
+        if (!finite_n(D->h_xi, 6 * D->F)) return VBH_EINVAL;
+    }
+    for (int f = 0; f < D->F; ++f) {
+        std::memcpy(D->base[f], h_poses + 12 * f, sizeof(D->base[f]));
+        if (d_xi)
+            compose_pose(h_poses + 12 * f, D->h_xi + 6 * f, D->cams.P[f]);
+        else
+            std::memcpy(D->cams.P[f], h_poses + 12 * f, sizeof(D->cams.P[f]));
+    }
+    D->with_xi = d_xi != nullptr;
+    const Cams &cams = D->cams;
     vbh_scene *s = D->s;
     if (int rc = scene_reset(s, st)) return rc;
     const unsigned g = unsigned(s->cus) * 8;
@@ -533,16 +664,16 @@ int vbh_diff_forward(vbh_diff *D, const float *d_depth, const float *h_poses, co
     return VBH_OK;
 }
 
-int vbh_diff_backward(vbh_diff *D, const float *d_depth, const float *h_poses, const int32_t *d_sample_frame,
-                      const int32_t *d_sample_pixel, int64_t n_samples, const float *d_grad_loss, float *d_grad_depth,
-                      float *d_grad_xi, void *stream) {
+int vbh_diff_backward(vbh_diff *D, const float *d_depth, const float *h_poses, const float *d_xi,
+                      const int32_t *d_sample_frame, const int32_t *d_sample_pixel, int64_t n_samples,
+                      const float *d_grad_loss, float *d_grad_depth, float *d_grad_xi, void *stream) {
     if (!D || !D->have_forward || !d_depth || !h_poses || !d_grad_loss || !d_grad_depth || !d_grad_xi ||
         n_samples < 0 || (n_samples > 0 && (!d_sample_frame || !d_sample_pixel)) ||
-        (n_samples + kSampleWG - 1) / kSampleWG > kMaxWG)
+        (n_samples + kSampleWG - 1) / kSampleWG > kMaxWG || (d_xi != nullptr) != D->with_xi ||
+        std::memcmp(h_poses, D->base, size_t(D->F) * 12 * sizeof(float)) != 0)
         return VBH_EINVAL;
     hipStream_t st = as_stream(stream);
-    Cams cams;
-    if (int rc = load_cams(D, h_poses, cams)) return rc;
+    const Cams &cams = D->cams;
     vbh_scene *s = D->s;
     const int64_t HW = int64_t(s->p.width) * s->p.height;
     const unsigned g = unsigned(s->cus) * 8;
@@ -557,7 +688,9 @@ int vbh_diff_backward(vbh_diff *D, const float *d_depth, const float *h_poses, c
     db.xi_part = D->d.xi_part + int64_t(gs) * D->F * 6;  // integration partials follow
     const unsigned gb = g < unsigned(kMaxWG) ? g : unsigned(kMaxWG);
     k_integrate_bwd<<<gb, kBlock, 0, st>>>(db, fr, cams, d_depth);
-    k_reduce_xi<<<unsigned(D->F * 6), kBlock, 0, st>>>(D->d, int(gs), int(gb), d_grad_xi);
+    double *g_left = static_cast<double *>(D->mem[7]);
+    k_reduce_xi<<<unsigned(D->F * 6), kBlock, 0, st>>>(D->d, int(gs), int(gb), g_left);
+    k_pose_grad<<<1, 64, 0, st>>>(g_left, d_xi, D->F, d_grad_xi);
     k_to_f32<<<g, kBlock, 0, st>>>(D->d.gd64, d_grad_depth, HW * D->F);
     VBH_LAUNCHED();
     return VBH_OK;

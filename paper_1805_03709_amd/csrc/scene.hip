@@ -150,7 +150,8 @@ __device__ __forceinline__ uint32_t set_hash(uint64_t k) {
 // Allocation (and, with mark, MC-set marking) of the 32x16-pixel tile (tx, ty) for update
 // seq.  Called by all kAllocThreads threads of a workgroup.
 __device__ __forceinline__ void alloc_tile(const Dev &S, const Frame &fr, const float *__restrict__ depth,
-                                           uint32_t frame, int seq, int mark, int tx, int ty, AllocShared &sh) {
+                                           const uint8_t *__restrict__ rgb, uint32_t frame, int seq, int mark, int tx,
+                                           int ty, AllocShared &sh) {
     unsigned long long *set = sh.set;
     unsigned long long *list = sh.list;
     int32_t *appended = sh.appended;
@@ -175,7 +176,13 @@ __device__ __forceinline__ void alloc_tile(const Dev &S, const Frame &fr, const 
     const int u = (tx * 4 + (wave & 3)) * 8 + lx;
     const int v = (ty * 2 + (wave >> 2)) * 8 + ly;
     const bool inb = u < fr.W && v < fr.H;
-    const float d = inb ? depth[int64_t(v) * fr.W + u] : 0.0f;
+    const uint32_t pix = inb ? uint32_t(v * fr.W + u) : 0u;
+    const float d = inb ? depth[pix] : 0.0f;
+    if (inb) {  // the pixel record that integration gathers: depth and colour in 8 bytes
+        uint32_t c = 0u;
+        if (rgb) c = uint32_t(rgb[3 * pix]) | uint32_t(rgb[3 * pix + 1]) << 8 | uint32_t(rgb[3 * pix + 2]) << 16;
+        S.PIX[pix] = make_uint2(__float_as_uint(d), c);
+    }
     const bool valid = inb && depth_valid(d, fr);
     const bool wave_any = __ballot(valid) != 0;  // uniform per wave
     const float xn = (float(u) - fr.cx) / fr.fx;
@@ -352,9 +359,10 @@ __device__ __forceinline__ void alloc_tile(const Dev &S, const Frame &fr, const 
 }
 
 __global__ void __launch_bounds__(kAllocThreads) k_alloc(Dev S, Frame fr, const float *__restrict__ depth,
-                                                         uint32_t frame, int seq, int mark) {
+                                                         const uint8_t *__restrict__ rgb, uint32_t frame, int seq,
+                                                         int mark) {
     __shared__ AllocShared sh;
-    alloc_tile(S, fr, depth, frame, seq, mark, int(blockIdx.x), int(blockIdx.y), sh);
+    alloc_tile(S, fr, depth, rgb, frame, seq, mark, int(blockIdx.x), int(blockIdx.y), sh);
 }
 
 __device__ __forceinline__ uint64_t first_lane64(uint64_t v) {
@@ -371,19 +379,24 @@ __device__ __forceinline__ uint64_t first_lane64(uint64_t v) {
 //   sdf < -mu.  Then F <- (W F + min(sdf, mu)) / (W + 1), W <- min(W + 1, 255) and each
 //   colour channel c <- (W c + c_obs + floor(n / 2)) / n with n = W + 1.
 
-// The eight voxels (lx, ly, 0..7) of a lane are projected first, then their depths are
-// loaded together, then the TSDF state (and observed colour) of the passing voxels is
-// loaded together; the slot of the wave's next block is fetched while the current one is
-// processed.  Each wave thus keeps up to 8 + 24 independent loads in flight.
-__global__ void __launch_bounds__(kBlock) k_integrate(Dev S, Frame fr, const float *__restrict__ depth,
-                                                      const uint8_t *__restrict__ rgb, int seq) {
+// The eight voxels (lx, ly, 0..7) of a lane are projected first, then their pixel records
+// (depth and colour, 8 bytes, written by the allocation kernel) are gathered together,
+// then the TSDF state of the passing voxels is loaded together; the slot of the wave's
+// next block is fetched while the current one is processed.  Offsets from wave-uniform
+// bases are 32-bit, so the loads take a scalar base plus a vector offset.
+__global__ void __launch_bounds__(kBlock) k_integrate(Dev S, Frame fr, int with_rgb, int seq, int timed) {
     const FrameCounters *fc = &S.C->fc[seq & (kRing - 1)];
     const int64_t n = fc->n_touched;
+    if (timed && blockIdx.x == 0 && threadIdx.x == 0) {  // the work of a timed update
+        atomicAdd(&S.C->timed_touched, (unsigned long long)n);
+        atomicAdd(&S.C->timed_mc, (unsigned long long)fc->n_mc);
+    }
     const int lane = lane_id();
     const int lx = lane & 7, ly = lane >> 3;
     const int64_t gw = int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6);
     const int64_t nw = int64_t(gridDim.x) * kWaves;
     const int32_t *touched = touched_of(S, seq);
+    const uint2 *__restrict__ pixrec = S.PIX;
     unsigned long long updates = 0;
     Slot cur = {};
     if (gw < n) cur = S.T[touched[gw]];
@@ -395,8 +408,8 @@ __global__ void __launch_bounds__(kBlock) k_integrate(Dev S, Frame fr, const flo
         unpack_key(first_lane64(cur.key), bx, by, bz);
         const float dlx = float(8 * bx + lx) * fr.vs - fr.P[3];
         const float dly = float(8 * by + ly) * fr.vs - fr.P[7];
-        float *const Fb = S.F + int64_t(pool) * 512 + lane;
-        uint32_t *const Wb = S.WRGB + int64_t(pool) * 512 + lane;
+        float *const Fb = S.F + int64_t(pool) * 512;  // wave-uniform block bases
+        uint32_t *const Wb = S.WRGB + int64_t(pool) * 512;
         int32_t pix[8];
         float pz[8];
 #pragma unroll
@@ -411,34 +424,33 @@ __global__ void __launch_bounds__(kBlock) k_integrate(Dev S, Frame fr, const flo
                 const float fu = floorf((fr.fx * (pcx / pcz) + fr.cx) + 0.5f);
                 const float fv = floorf((fr.fy * (pcy / pcz) + fr.cy) + 0.5f);
                 if (fu >= 0.0f && fu < float(fr.W) && fv >= 0.0f && fv < float(fr.H))
-                    pix[j] = int32_t(fv) * fr.W + int32_t(fu);
+                    pix[j] = int32_t(__umul24(uint32_t(fv), uint32_t(fr.W)) + uint32_t(fu));
             }
         }
-        float d[8];
+        // a voxel outside the image reads pixel 0 (any valid address) and is dropped below
+        uint2 rec[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) d[j] = pix[j] >= 0 ? depth[pix[j]] : 0.0f;
+        for (int j = 0; j < 8; ++j)
+            rec[j] = *reinterpret_cast<const uint2 *>(reinterpret_cast<const char *>(pixrec) +
+                                                      (uint32_t(pix[j] >= 0 ? pix[j] : 0) << 3));
         const Slot nxt = next_idx >= 0 ? S.T[next_idx] : Slot{};
         bool ok[8];
+        float d[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) ok[j] = pix[j] >= 0 && depth_valid(d[j], fr) && !(d[j] - pz[j] < -fr.mu);
+        for (int j = 0; j < 8; ++j) {
+            d[j] = __uint_as_float(rec[j].x);
+            ok[j] = pix[j] >= 0 && depth_valid(d[j], fr) && !(d[j] - pz[j] < -fr.mu);
+        }
         const uint32_t col = pool >= 0 ? S.SGN[int64_t(pool) * 64 + lane] : 0u;  // this lane's column
         float F[8];
         uint32_t w[8];
-        uint32_t rg[8], bl[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             F[j] = 0.0f;
             w[j] = 0u;
-            rg[j] = 0u;
-            bl[j] = 0u;
             if (ok[j]) {
-                F[j] = Fb[64 * j];
-                w[j] = Wb[64 * j];
-                if (rgb) {
-                    const uint8_t *o = rgb + int64_t(pix[j]) * 3;
-                    rg[j] = o[0];
-                    bl[j] = uint32_t(o[1]) | uint32_t(o[2]) << 8;
-                }
+                F[j] = Fb[uint32_t(lane + 64 * j)];
+                w[j] = Wb[uint32_t(lane + 64 * j)];
             }
         }
         float Fn[8];
@@ -451,20 +463,20 @@ __global__ void __launch_bounds__(kBlock) k_integrate(Dev S, Frame fr, const flo
             const uint32_t w_old = w[j] & 0xFFu;
             const float wf = float(w_old);
             const float inv = __builtin_amdgcn_rcpf(wf + 1.0f);
-            Fn[j] = (wf * F[j] + tsdf) * inv;
+            Fn[j] = fmaf(wf, F[j], tsdf) * inv;
             uint32_t out = w_old == 255u ? 255u : w_old + 1u;
-            if (rgb) {
-                // c <- floor((W c + c_obs + floor(n/2)) / n).  The numerator plus 1/2 is formed
-                // exactly in float (integers below 2^17); its true quotient then lies at least
-                // 1/(2n) >= 1/512 away from an integer, while the product with the reciprocal
-                // is off by at most 256 * 2^-22, so truncation gives the exact floor.
+            if (with_rgb) {
+                // c <- floor((W c + c_obs + floor(n/2)) / n).  The numerator plus 1/2 is exact in
+                // float (integers below 2^17, so the fused multiply-add rounds nothing); its
+                // true quotient lies at least 1/(2n) >= 1/512 away from an integer, while the
+                // product with the reciprocal is off by at most 256 * 2^-22, so truncation
+                // gives the exact floor.
                 const float half = float((w_old + 1u) >> 1) + 0.5f;
-                const uint32_t o3 = rg[j] | bl[j] << 8;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     const float cur_c = float((w[j] >> (8 * (c + 1))) & 0xFFu);
-                    const float obs_c = float((o3 >> (8 * c)) & 0xFFu);
-                    const float num = wf * cur_c + (obs_c + half);
+                    const float obs_c = float((rec[j].y >> (8 * c)) & 0xFFu);
+                    const float num = fmaf(wf, cur_c, obs_c + half);
                     out |= uint32_t(num * inv) << (8 * (c + 1));
                 }
             } else {
@@ -475,8 +487,8 @@ __global__ void __launch_bounds__(kBlock) k_integrate(Dev S, Frame fr, const flo
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             if (ok[j]) {
-                Fb[64 * j] = Fn[j];
-                Wb[64 * j] = Wn[j];
+                Fb[uint32_t(lane + 64 * j)] = Fn[j];
+                Wb[uint32_t(lane + 64 * j)] = Wn[j];
                 ++updates;
             }
         }
@@ -1158,8 +1170,10 @@ int scene_fuse(vbh_scene *s, const float *d_depth, const uint8_t *d_rgb, const f
     const int seq = s->seq;
     StageTimer *tm = timer_for(s, seq);
     const unsigned g = unsigned(s->cus) * 8;
-    launch(tm, 0, st, k_alloc, alloc_grid(s), dim3(kAllocThreads), s->d, fr, d_depth, frame, seq, int(with_mc));
-    launch(tm, 1, st, k_integrate, dim3(g), dim3(kBlock), s->d, fr, d_depth, d_rgb, seq);
+    launch(tm, 0, st, k_alloc, alloc_grid(s), dim3(kAllocThreads), s->d, fr, d_depth, d_rgb, frame, seq,
+           int(with_mc));
+    launch(tm, 1, st, k_integrate, dim3(g), dim3(kBlock), s->d, fr, int(d_rgb != nullptr), seq,
+           int(tm != nullptr && with_mc));
     if (with_mc) launch(tm, 3, st, k_mc_extract, dim3(g), dim3(kBlock), s->d, seq, int(g), frame);
     VBH_LAUNCHED();
     s->seq = seq + 1;
@@ -1229,7 +1243,7 @@ int scene_fuse_frames_host(vbh_scene *s, const float *h_depth, const uint8_t *h_
 int scene_alloc_only(vbh_scene *s, const float *d_depth, const float *pose, uint32_t frame, hipStream_t st) {
     const int seq = s->seq;
     launch(timer_for(s, seq), 0, st, k_alloc, alloc_grid(s), dim3(kAllocThreads), s->d, make_frame(s, pose), d_depth,
-           frame, seq, 0);
+           static_cast<const uint8_t *>(nullptr), frame, seq, 0);
     VBH_LAUNCHED();
     s->seq = seq + 1;
     s->last_frame = frame;
@@ -1264,7 +1278,8 @@ int vbh_scene_create(const vbh_params *p, vbh_scene **out) {
     *out = nullptr;
     if (!is_pow2(p->slots) || p->slots < 64 || p->slots > (1ull << 31) || p->pool_blocks < 1 ||
         p->pool_blocks > (int64_t(1) << 30) || p->log_capacity < 1 || !(p->voxel_size > 0) ||
-        !(p->trunc >= p->voxel_size) || p->width <= 0 || p->height <= 0 || !(p->fx > 0) || !(p->fy > 0) ||
+        !(p->trunc >= p->voxel_size) || p->width <= 0 || p->height <= 0 || p->width > 16384 ||
+        p->height > 16384 || !(p->fx > 0) || !(p->fy > 0) ||
         p->hash_kind < 0 || p->hash_kind > 1 || !(p->depth_max >= p->depth_min))
         return VBH_EINVAL;
     vbh_scene *s = new (std::nothrow) vbh_scene();
@@ -1277,8 +1292,8 @@ int vbh_scene_create(const vbh_params *p, vbh_scene **out) {
     const size_t sizes[] = {p->slots * sizeof(Slot), P * 512 * sizeof(float), P * 512 * 4, P * 512 * 4,
                             P * 8,                  P * 4,                     2 * p->slots * 4, 2 * P * 4,
                             size_t(p->log_capacity) * 8, size_t(s->max_chunks) * 8, sizeof(Counters), 64 * 8,
-                            size_t(kMaxPartials) * 8, P * 64 * 2};
-    for (int i = 0; i < 14; ++i) {
+                            size_t(kMaxPartials) * 8, P * 64 * 2, size_t(p->width) * size_t(p->height) * 8};
+    for (int i = 0; i < 15; ++i) {
         if (hipMalloc(&s->mem[i], sizes[i]) != hipSuccess) {
             vbh_scene_destroy(s);
             return VBH_ENOMEM;
@@ -1304,6 +1319,7 @@ int vbh_scene_create(const vbh_params *p, vbh_scene **out) {
     s->hostbuf = static_cast<unsigned long long *>(s->mem[11]);
     d.partial = static_cast<unsigned long long *>(s->mem[12]);
     d.SGN = static_cast<uint16_t *>(s->mem[13]);
+    d.PIX = static_cast<uint2 *>(s->mem[14]);
     bool ok = vbh::table_init(d.T, p->slots, nullptr) == VBH_OK;
     for (int i : {1, 2, 3, 4, 5, 13})
         if (ok) ok = hipMemset(s->mem[i], 0, sizes[i]) == hipSuccess;
@@ -1499,9 +1515,16 @@ int vbh_scene_enable_timing(vbh_scene *s, int32_t period) {
     return VBH_OK;
 }
 
-int vbh_scene_timing(vbh_scene *s, double *ms_out, int64_t *h_frames, void *stream) {
+int vbh_scene_timing(vbh_scene *s, double *ms_out, int64_t *h_frames, int64_t *h_blocks, void *stream) {
     if (!s || !ms_out) return VBH_EINVAL;
     VBH_HIP(hipStreamSynchronize(as_stream(stream)));
+    unsigned long long blk[2] = {0, 0};
+    VBH_HIP(hipMemcpy(blk, &s->C->timed_touched, sizeof(blk), hipMemcpyDeviceToHost));
+    VBH_HIP(hipMemset(&s->C->timed_touched, 0, sizeof(blk)));
+    if (h_blocks) {
+        h_blocks[0] = int64_t(blk[0]);
+        h_blocks[1] = int64_t(blk[1]);
+    }
     for (int i = 0; i < 4; ++i) ms_out[i] = 0.0;
     for (auto &tm : s->ev_pending) {
         for (int i = 0; i < kStages; ++i) {

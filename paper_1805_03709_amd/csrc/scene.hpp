@@ -52,7 +52,8 @@ struct Counters {
     uint32_t err;
     uint32_t pad;
     unsigned long long visible;  // result count of the last visible-block selection
-    uint32_t pad2[4];
+    unsigned long long timed_touched;  // touched and MC-set blocks of the updates whose
+    unsigned long long timed_mc;       // kernels were timed, since the last timing read
 };
 
 // Device view of a scene, passed by value to kernels.
@@ -72,6 +73,8 @@ struct Dev {
     uint64_t *log;       // [L] (frame << 32) | pool
     int64_t *prefix;     // [max_chunks + 1] scratch of the paged walk
     unsigned long long *partial;  // [kMaxPartials] per-workgroup statistics, reduced later
+    uint2 *PIX;          // [H*W] the current frame's pixels as written by the allocation kernel:
+                         // x = depth bits, y = r | g << 8 | b << 16 (0 without colour)
     int64_t pool_cap;
     uint64_t log_cap;
     Counters *C;
@@ -115,7 +118,7 @@ struct vbh_scene {
     int seq = 0;        // number of updates so far (ring index of the next one)
     int cus = 256;      // compute units of the device the scene lives on
     uint32_t last_frame = 0;
-    void *mem[14] = {};
+    void *mem[15] = {};
     int timing_period = 0;  // time the kernels of every n-th update (0: off)
     // the host-input multi-frame form's two device frame buffers (depth then colour),
     // allocated on first use

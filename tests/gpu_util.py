@@ -35,3 +35,29 @@ def sort_keys(keys):
     k = np.asarray(keys).reshape(-1, 3)
     order = np.lexsort((k[:, 2], k[:, 1], k[:, 0]))
     return k[order], order
+
+
+CORNERS = np.array([(0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0), (0, 0, 1), (1, 0, 1), (1, 1, 1), (0, 1, 1)])
+
+
+def corner_min_abs(O, keys, blk, loc):
+    """min over the 8 cell corners of |F_oracle| for the voxels (keys[blk], local loc),
+    read from oracle scene O in one call (absent or unobserved corners read as 0)."""
+    blk, loc = np.asarray(blk), np.asarray(loc)
+    if blk.size == 0:
+        return np.zeros(0)
+    g = keys[blk].astype(np.int64) * 8 + np.stack([loc % 8, (loc // 8) % 8, loc // 64], -1)
+    cs = g[:, None, :] + CORNERS[None]                      # [m, 8, 3]
+    B = np.floor_divide(cs, 8)
+    uniq, inv = np.unique(B.reshape(-1, 3), axis=0, return_inverse=True)
+    F, _, _, _ = O.read(uniq.astype(np.int32))
+    lc = cs - 8 * B
+    li = (lc[..., 0] + 8 * lc[..., 1] + 64 * lc[..., 2]).reshape(-1)
+    return np.abs(F[inv.reshape(-1), li]).reshape(-1, 8).min(axis=1)
+
+
+def pack_mc(mc, rgb):
+    """uint8 index [.., 512] and RGB [.., 512, 3] -> the 4-byte MC voxel as int64."""
+    m = torch.as_tensor(mc).to(torch.int64)
+    c = torch.as_tensor(rgb).to(torch.int64)
+    return m | c[..., 0] << 8 | c[..., 1] << 16 | c[..., 2] << 24

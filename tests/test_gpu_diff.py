@@ -13,12 +13,13 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-4
 
 
-def run_gpu(vbh, vol, cam, depth, poses, sf, sp):
+def run_gpu(vbh, vol, cam, depth, poses, sf, sp, xi=None):
     from paper_1805_03709_amd.autograd import DiffFusion
     E = DiffFusion(vbh.make_params(vol, cam), depth.shape[0])
     d, f, p = to_dev(depth), to_dev(sf), to_dev(sp)
-    loss, fs = E.vbh_diff_forward(d, poses, f, p)
-    gD, gxi = E.vbh_diff_backward(d, poses, f, p, torch.ones((), device="cuda"))
+    x = None if xi is None else to_dev(np.asarray(xi, np.float32))
+    loss, fs = E.vbh_diff_forward(d, poses, f, p, xi=x)
+    gD, gxi = E.vbh_diff_backward(d, poses, f, p, torch.ones((), device="cuda"), xi=x)
     return E, float(loss.cpu()), fs.cpu().numpy(), gD.cpu().numpy().reshape(depth.shape[0], -1), gxi.cpu().numpy()
 
 
@@ -94,3 +95,33 @@ def test_autograd_function_matches_abi():
     assert abs(float(loss.detach()) - float(l2)) <= 1e-6 * float(l2)
     assert torch.allclose(d.grad, gD, rtol=1e-5, atol=1e-9)
     assert torch.allclose(xi.grad, gxi, rtol=1e-5, atol=1e-9)
+
+
+def test_nonzero_xi_against_oracle(orc):
+    """Poses Exp(xi) T0 at a nonzero xi: the library composes them, and its dL/dxi (left
+    gradient through J_l(xi)^T) matches the oracle's analytic gradient at that reference
+    point and 5-point differences of L(Exp(xi + h e) T0); the autograd function returns
+    the same gradients as the ABI."""
+    vbh = require_gpu()
+    import sys, os
+    sys.path.insert(0, os.path.dirname(__file__))
+    from test_oracle_diff import VOL, XI_REF, small_problem
+    from paper_1805_03709_amd.autograd import DiffFusion, TSDFSampleLoss
+    cam, depth, poses, sf, sp = small_problem()
+    xi32 = XI_REF.astype(np.float32)
+    say("[diff nonzero xi]")
+    E, loss, fs, gD, gxi = run_gpu(vbh, VOL, cam, depth, poses, sf, sp, xi=xi32)
+    O = orc.Diff(VOL, cam, depth, poses, sf, sp, xi_ref=xi32.astype(np.float64))
+    check(orc, O, loss, fs, gD, gxi)
+    # through autograd
+    E2 = DiffFusion(vbh.make_params(VOL, cam), depth.shape[0])
+    d = to_dev(depth).requires_grad_(True)
+    xi = to_dev(xi32).requires_grad_(True)
+    l2 = TSDFSampleLoss.apply(d, xi, E2, poses, to_dev(sf), to_dev(sp))
+    l2.backward()
+    assert abs(float(l2.detach()) - loss) <= 1e-6 * loss
+    assert np.allclose(xi.grad.cpu().numpy(), gxi, rtol=1e-5, atol=1e-9)
+    assert np.allclose(d.grad.cpu().numpy().reshape(gD.shape), gD, rtol=1e-5, atol=1e-9)
+    # the backward refuses inputs other than the forward's
+    with pytest.raises(vbh.VbhError):
+        E.vbh_diff_backward(to_dev(depth), poses, to_dev(sf), to_dev(sp), torch.ones((), device="cuda"))

@@ -96,7 +96,7 @@ def test_adversarial_same_key_batches(kind):
     assert len(keyset(gk)) == gk.shape[0]
 
 
-@pytest.mark.parametrize("kind", [0])
+@pytest.mark.parametrize("kind", [0, 1])
 def test_full_size_bulk_and_mixed(kind):
     """2^24 keys (2^23 unique) into 2^25 slots, then 16 mixed 1M-op batches; checked by set
     algebra at full size and against the oracle on a sample of keys."""
@@ -158,3 +158,11 @@ def test_errors_are_reported():
     assert (m.vbh_find(to_dev(bad)).cpu().numpy() == ABSENT).all()
     m.vbh_map_status()
     assert m.vbh_map_size() == (0, 0)
+    # the reserved value is refused at insert; the key stays absent and a find returns at once
+    k = np.array([[3, 4, 5], [6, 7, 8]], np.int32)
+    for mm in (m, vbh.ChainedMap(64, 64, 0)):
+        st = mm.vbh_insert(to_dev(k), to_dev(np.array([ABSENT, 9], np.int32))).cpu().numpy()
+        assert st.tolist() == [-1, 1]
+        assert mm.vbh_map_status() == vbh.binding.VBH_EINVAL
+        assert mm.vbh_find(to_dev(k)).cpu().numpy().tolist() == [ABSENT, 9]
+        assert mm.vbh_map_status() == 0

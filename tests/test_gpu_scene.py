@@ -9,11 +9,10 @@ import pytest
 import torch
 
 from datagen import configs
-from gpu_util import keyset, require_gpu, say, sort_keys, to_dev
+from gpu_util import corner_min_abs, keyset, require_gpu, say, sort_keys, to_dev
 
 pytestmark = pytest.mark.gpu
 F_TOL = 1e-5
-OFFS = np.array([(0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0), (0, 0, 1), (1, 0, 1), (1, 1, 1), (0, 1, 1)])
 
 
 def pose_np(p):
@@ -44,20 +43,6 @@ def integrate_both(G, O, depth, rgb, poses, frames, first_id=1, check_frames=Tru
     assert G.vbh_scene_status() == 0
 
 
-def corner_min_abs(O, keys, mism):
-    """min over the 8 corners of |F_oracle| for mismatched voxels (block i, local l)."""
-    out = []
-    for i, l in zip(*mism):
-        g = keys[i].astype(np.int64) * 8 + np.array([l % 8, (l // 8) % 8, l // 64])
-        cs = g[None] + OFFS
-        B = np.floor_divide(cs, 8)
-        F, W, _, found = O.read(B.astype(np.int32))
-        loc = cs - 8 * B
-        li = loc[:, 0] + 8 * loc[:, 1] + 64 * loc[:, 2]
-        out.append(np.abs(F[np.arange(8), li]).min())
-    return np.array(out)
-
-
 def compare_state(G, O):
     gk = G.vbh_scene_export_blocks().cpu().numpy()
     ok = O.blocks()
@@ -78,7 +63,7 @@ def compare_state(G, O):
     mism = np.nonzero(gmc != omc)
     say(f"  MC end-to-end mismatches: {mism[0].size}")
     if mism[0].size:
-        assert (corner_min_abs(O, keys, mism) <= F_TOL).all()
+        assert (corner_min_abs(O, keys, *mism) <= F_TOL).all()
     return keys, F, W, rgb, gmc, grgb
 
 
@@ -267,14 +252,20 @@ def test_multi_frame_form_equals_per_frame_calls(orc):
     d, c = depth.cuda(), rgb.cuda()
     params = vbh.make_params(configs.FULL_VOL, configs.FULL_CAM)
     A, B = vbh.Scene(params), vbh.Scene(params)
+    per_frame = []
     for f in range(n):
         A.vbh_integrate_frame(d[f], c[f], poses[f], f + 1)
+        st = A.vbh_scene_stats()
+        per_frame.append((st["n_touched"], st["n_mc"]))
     B.vbh_scene_enable_timing(2)
     B.vbh_integrate_frames(d[:4].contiguous(), c[:4].contiguous(), poses[:4], 1)
     B.vbh_integrate_frames(d[4:].contiguous(), c[4:].contiguous(), poses[4:], 5)
     assert A.vbh_scene_status() == 0 and B.vbh_scene_status() == 0
-    ms, timed = B.vbh_scene_timing()
+    ms, timed, blocks = B.vbh_scene_timing(with_blocks=True)
     assert timed == n // 2 and ms["alloc"] > 0 and ms["integrate"] > 0 and ms["mc_extract"] > 0
+    # the block counts of exactly the timed updates (every second one, from the first)
+    assert blocks == tuple(int(sum(x[i] for x in per_frame[::2])) for i in range(2))
+    assert B.vbh_scene_timing(with_blocks=True)[1:] == (0, (0, 0))  # reset by the read
     same_scene(A, B)
     with pytest.raises(vbh.VbhError):
         B.vbh_integrate_frames(d[:1].contiguous(), c[:1].contiguous(), poses[:1], n)  # id not increasing
@@ -304,3 +295,59 @@ def test_host_input_frames_equal_device_input():
     same_scene(A, B)
     with pytest.raises(TypeError):
         B.vbh_integrate_frames_host(depth[:1].cuda(), None, poses[:1], n + 1)  # device tensor refused
+
+
+def test_saturated_weights(orc):
+    """Blocks written with W in {254, 255} (and a few 0 and 253), mixed colours and F, then
+    three frames fused on top: the running mean at saturation (n = 256, W stays 255) for F
+    and colour, W and RGB bit-exact and F within 1e-5 m of the oracle."""
+    vbh = require_gpu()
+    _, depth, rgb, poses = configs.tiny_inputs(8)
+    G, O = make_pair(vbh, orc, configs.TINY_VOL, configs.TINY_CAM)
+    integrate_both(G, O, depth, rgb, poses, range(2))
+    keys, _ = sort_keys(O.blocks())
+    rng = np.random.default_rng(255)
+    F = rng.uniform(-0.04, 0.04, (keys.shape[0], 512)).astype(np.float32)
+    W = rng.choice(np.array([0, 253, 254, 255, 255, 255], np.uint8), size=F.shape)
+    c = rng.integers(0, 256, size=F.shape + (3,)).astype(np.uint8)
+    G.vbh_scene_write_blocks(to_dev(keys), to_dev(F), to_dev(W), to_dev(c), 3)
+    assert O.write(keys, F, W, c, 3) == 0
+    integrate_both(G, O, depth, rgb, poses, [2, 3, 4], first_id=4)
+    k2, F2, W2, rgb2, gmc, grgb = compare_state(G, O)
+    # the saturation branch was taken: voxels written at 255 that were observed again
+    pos = {tuple(k): i for i, k in enumerate(k2.tolist())}
+    idx = np.array([pos[tuple(k)] for k in keys.tolist()])
+    sat = (W == 255) & ((F2[idx] != F) | np.any(rgb2[idx] != c, axis=-1))
+    from254 = (W == 254) & (W2[idx] == 255)
+    say(f"  saturated voxels updated: {sat.sum()}, 254 -> 255: {from254.sum()}")
+    assert sat.sum() > 1000 and from254.sum() > 100
+    assert (W2[idx][W == 255] == 255).all()
+    mc_on_identical_input(orc, configs.TINY_VOL, configs.TINY_CAM, k2, F2, W2, rgb2, gmc, grgb)
+
+
+def test_full_size_long_run(orc):
+    """150 frames of the 640x480 noisy sequence at 5 mm voxels in the full-size volume:
+    touched, new and MC sets bit-exact on every 10th frame, then the whole final state
+    (revisited blocks, weights up to the frame count) against the oracle."""
+    vbh = require_gpu()
+    n = 150
+    say(f"[scene full long] generating {n} frames")
+    _, depth, rgb, poses = configs.full_inputs(range(n), device="cuda")
+    depth, rgb = depth.contiguous(), rgb.contiguous()
+    hd, hc = depth.cpu().numpy(), rgb.cpu().numpy()
+    G, O = make_pair(vbh, orc, configs.FULL_VOL, configs.FULL_CAM)
+    for f in range(n):
+        G.vbh_integrate_frame(depth[f], rgb[f], poses[f], f + 1)
+        assert O.integrate(hd[f], hc[f], poses[f], f + 1) == 0
+        if f % 10 == 9:
+            st = G.vbh_scene_stats()
+            gt, ot = keyset(G.vbh_scene_last_touched()), keyset(O.last_touched())
+            assert gt == ot, (f, len(gt), len(ot))
+            assert st["n_new"] == len(O.last_new())
+            assert keyset(G.vbh_scene_last_mc()) == keyset(O.last_mc_updated())
+            say(f"  frame {f + 1}: touched {len(gt)} new {st['n_new']} blocks {st['n_blocks']}")
+    assert G.vbh_scene_status() == 0
+    keys, F, W, rgb_, gmc, grgb = compare_state(G, O)
+    say(f"  max W {W.max()}")
+    assert W.max() >= 100
+    mc_on_identical_input(orc, configs.FULL_VOL, configs.FULL_CAM, keys, F, W, rgb_, gmc, grgb)

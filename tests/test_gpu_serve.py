@@ -5,25 +5,70 @@
 - the selection equals vbh_updated_blocks_since and the MC voxels equal the MC pool;
 - with frames fused concurrently, each result equals the expected page at the request's
   scene version, computed from the append-only update log;
-- admission by memory, request-size errors, reconnection from cursor 0.
+- admission by memory, request-size errors, reconnection from cursor 0;
+- against the oracle's serving replay (per-client stream sets, Sec. 4.2): replayed in
+  order of scene version, every answer is a valid answer of its client's stream set (its
+  size, no block twice, only owed blocks, oldest updates first), and its MC voxels equal
+  the oracle's at that version - bit-exact on an analytically written scene of 150k
+  blocks with request sizes log-uniform up to 10^5, and on fused scenes wherever no cell
+  corner has |F_oracle| <= 1e-5.
 """
 import numpy as np
 import pytest
 import torch
 
 from datagen import configs
-from gpu_util import keyset, require_gpu, say
+import oracle
+from gpu_util import corner_min_abs, keyset, pack_mc, require_gpu, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
 
-def tiny_scene(vbh, n_frames):
+def tiny_scene(vbh, n_frames, with_oracle=False):
     _, depth, rgb, poses = configs.tiny_inputs(32)
     S = vbh.Scene(vbh.make_params(configs.TINY_VOL, configs.TINY_CAM))
+    O = oracle.Scene(configs.TINY_VOL, configs.TINY_CAM) if with_oracle else None
     for f in range(n_frames):
         S.vbh_integrate_frame(depth[f].cuda(), rgb[f].cuda(), poses[f], f + 1)
+        if O is not None:
+            assert O.integrate(depth[f].numpy(), rgb[f].numpy(), poses[f], f + 1) == 0
     assert S.vbh_scene_status() == 0
+    if with_oracle:
+        return S, O, depth, rgb, poses
     return S, depth.cuda(), rgb.cuda(), poses
+
+
+def oracle_replay(O, n_clients, clients, limits, res, outs, advance=None, exact_mc=False):
+    """Replays the served requests against the oracle's per-client stream sets, version by
+    version (advance(v) brings the oracle scene to version v).  Every GPU answer must be a
+    valid answer of its client's set; its MC voxels are compared with the oracle's stored MC
+    voxels at that version: bit-exact when exact_mc, else differences only at cells with a
+    corner |F_oracle| <= 1e-5.  Returns (blocks checked, MC voxels allowed to differ)."""
+    T = oracle.Streams(O, n_clients)
+    order = np.lexsort((np.arange(len(clients)), res["version"]))
+    blocks, near = 0, 0
+    for i in order:
+        v = int(res["version"][i])
+        if advance is not None:
+            advance(v)
+        T.sync()
+        k = int(res["count"][i])
+        keys = outs[i][0][:k].cpu().numpy()
+        rc = T.take(int(clients[i]), int(limits[i]), keys)
+        assert rc == 0, (i, int(clients[i]), v, k, rc)
+        if k == 0:
+            continue
+        omc, orgb = O.stored_mc(keys)
+        want = pack_mc(omc, orgb).numpy()
+        got = outs[i][1][:k].cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+        bad = np.nonzero(got != want)
+        if exact_mc:
+            assert bad[0].size == 0, (i, bad[0].size)
+        elif bad[0].size:
+            assert (corner_min_abs(O, keys, *bad) <= 1e-5).all(), i
+            near += bad[0].size
+        blocks += k
+    return blocks, near
 
 
 def out_buffers(limits):
@@ -37,7 +82,7 @@ def log_uniform(rng, n, lo, hi):
 
 def test_alone_equals_mix_static_scene():
     vbh = require_gpu()
-    S, _, _, _ = tiny_scene(vbh, 32)
+    S, O, _, _, _ = tiny_scene(vbh, 32, with_oracle=True)
     nb = S.vbh_scene_stats()["n_blocks"]
     srv = vbh.Server(S, arena_bytes=256 << 20, max_inflight=32, n_streams=4, n_clients=8, max_batch=12)
     rng = np.random.default_rng(0)
@@ -49,6 +94,9 @@ def test_alone_equals_mix_static_scene():
     res = srv.vbh_server_run(clients, limits, arrivals, outs)
     assert (res["status"] == 0).all()
     say(f"[serve static] {nb} blocks, {n} requests, {res['count'].sum()} blocks served")
+    blocks, near = oracle_replay(O, 8, clients, limits, res, outs)
+    say(f"[serve static] oracle replay: {blocks} blocks, {near} MC voxels at |F| <= 1e-5")
+    assert blocks == res["count"].sum()
     # continuous batching: some request was admitted while an earlier one was in flight
     overl = [(i, j) for i in range(n) for j in range(n)
              if res["admit_s"][i] < res["admit_s"][j] < res["done_s"][i]]
@@ -105,7 +153,8 @@ def expected_pages(fr, keys, cursor, limit, version):
 
 def test_concurrent_integration_versions():
     vbh = require_gpu()
-    S, depth, rgb, poses = tiny_scene(vbh, 8)
+    S, O, hdepth, hrgb, poses = tiny_scene(vbh, 8, with_oracle=True)
+    depth, rgb = hdepth.cuda(), hrgb.cuda()
     srv = vbh.Server(S, arena_bytes=512 << 20, max_inflight=64, n_streams=4, n_clients=8, max_batch=16)
     frames = [(depth[f].contiguous(), rgb[f].contiguous(), poses[f], 0.004 * (f - 7), f + 1) for f in range(8, 32)]
     rng = np.random.default_rng(1)
@@ -142,6 +191,58 @@ def test_concurrent_integration_versions():
             checked_mc += int(final.sum())
     say(f"[serve concurrent] {n} requests checked against the log; MC voxels checked for {checked_mc} blocks")
     assert checked_mc > 1000
+    # the oracle, fused in step with the served versions
+    at = [8]
+
+    def advance(v):
+        while at[0] < v:
+            f = at[0]
+            assert O.integrate(hdepth[f].numpy(), hrgb[f].numpy(), poses[f], f + 1) == 0
+            at[0] += 1
+
+    blocks, near = oracle_replay(O, 8, clients, limits, res, outs, advance=advance)
+    say(f"[serve concurrent] oracle replay: {blocks} blocks over {vers.size} versions, "
+        f"{near} MC voxels at |F| <= 1e-5")
+    assert blocks == res["count"].sum()
+
+
+def test_large_written_scene_against_oracle():
+    """150k blocks of the serving scene written analytically (two updates), 8 clients,
+    48 requests with sizes log-uniform in [10^2, 10^5] arriving together: every answer and
+    its MC voxels against the oracle's stream sets, bit-exact."""
+    vbh = require_gpu()
+    say("[serve large] building analytic blocks")
+    keys, F, W, rgb = configs.analytic_blocks(configs.serve_scene(), configs.SERVE_VOL.voxel_size,
+                                              configs.SERVE_VOL.trunc, device="cuda")
+    n_blk = 150_000
+    keys, F, W, rgb = (t[:n_blk].contiguous() for t in (keys, F, W, rgb))
+    vol = configs.Volume(**{**configs.SERVE_VOL.__dict__, "slots": 1 << 19, "pool_blocks": 1 << 18,
+                            "log_capacity": 1 << 21})
+    S = vbh.Scene(vbh.make_params(vol, configs.FULL_CAM))
+    O = oracle.Scene(vol, configs.FULL_CAM)
+    hk, hF, hW, hc = (t.cpu().numpy() for t in (keys, F, W, rgb))
+    half = n_blk // 2
+    for lo, hi, fid in ((0, half, 1), (half, n_blk, 2)):
+        S.vbh_scene_write_blocks(keys[lo:hi], F[lo:hi], W[lo:hi], rgb[lo:hi], fid)
+        assert O.write(hk[lo:hi], hF[lo:hi], hW[lo:hi], hc[lo:hi], fid) == 0
+    assert S.vbh_scene_status() == 0 and S.vbh_scene_stats()["n_blocks"] == n_blk
+    assert S.vbh_scene_stats()["log_length"] == O.log_length()
+    del F, W, rgb
+    rng = np.random.default_rng(6464)
+    n = 48
+    clients = np.arange(n) % 8
+    limits = log_uniform(rng, n, 100, 100_000)
+    limits[3] = 100_000
+    arrivals = np.zeros(n)
+    outs = out_buffers(limits)
+    srv = vbh.Server(S, arena_bytes=1 << 30, max_inflight=32, n_streams=4, n_clients=8, max_batch=16)
+    res = srv.vbh_server_run(clients, limits, arrivals, outs)
+    assert (res["status"] == 0).all()
+    say(f"[serve large] {n} requests, {res['count'].sum()} blocks served, "
+        f"largest answer {res['count'].max()}")
+    assert res["count"].max() == 100_000
+    blocks, _ = oracle_replay(O, 8, clients, limits, res, outs, exact_mc=True)
+    assert blocks == res["count"].sum()
 
 
 def test_admission_by_memory_and_errors():
