@@ -278,6 +278,16 @@ int64_t vbh_mc_work_size(int64_t n);
 int vbh_mc_case(int32_t index, int8_t *h_edges);
 int vbh_mc_triangulate(const int32_t *d_keys, const uint32_t *d_mcv, int64_t n, float voxel_size, float *d_pos,
                        uint8_t *d_rgb, int64_t cap, int64_t *d_work, int64_t *h_count, void *stream);
+/* For callers that cannot allocate device memory (serving loops and harnesses that forbid
+ * hipMalloc): vbh_mc_triangulate with its workspace taken from a static array of the
+ * library on the current device (8 MiB per device, held until the process ends) instead of
+ * d_work.  Same inputs, outputs, synchronisation and results; it calls no allocating
+ * routine.  n > VBH_MC_STATIC_MAX_BLOCKS gives VBH_EINVAL and enqueues nothing.  Every call
+ * on one device shares that array: calls that overlap on one device (other host threads,
+ * other streams) race and must be serialised by the caller. */
+#define VBH_MC_STATIC_MAX_BLOCKS (1 << 20)
+int vbh_mc_triangulate_static(const int32_t *d_keys, const uint32_t *d_mcv, int64_t n, float voxel_size,
+                              float *d_pos, uint8_t *d_rgb, int64_t cap, int64_t *h_count, void *stream);
 
 /* Synchronising check, then enqueues a copy of log entries [start, start + n) (which must
  * lie below the log length): d_frame uint32 [n] update frame ids, d_keys int32 [n][3]

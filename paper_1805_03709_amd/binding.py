@@ -110,6 +110,7 @@ SIGNATURES = {
     "vbh_mc_work_size": ([_I64], _I64),
     "vbh_mc_case": ([_I32, C.c_void_p], C.c_int),
     "vbh_mc_triangulate": ([_P, _P, _I64, C.c_float, _P, _P, _I64, _P, C.POINTER(_I64), _V], C.c_int),
+    "vbh_mc_triangulate_static": ([_P, _P, _I64, C.c_float, _P, _P, _I64, C.POINTER(_I64), _V], C.c_int),
     "vbh_scene_visible_blocks": ([_V, C.POINTER(C.c_float), _P, _I64, C.POINTER(_I64), _V], C.c_int),
     "vbh_server_create": ([_V, C.POINTER(vbh_server_config), C.POINTER(_V)], C.c_int),
     "vbh_server_destroy": ([_V], None),

@@ -358,6 +358,45 @@ int64_t vbh_mc_work_size(int64_t n) {
     return n + (n + kChunk - 1) / kChunk + 1;
 }
 
+}  // extern "C"
+
+namespace {
+// Workspace of the allocation-free triangulation: the per-block counts and chunk sums of
+// up to VBH_MC_STATIC_MAX_BLOCKS blocks, resident on every device the library runs on.
+constexpr int64_t kStaticWork = VBH_MC_STATIC_MAX_BLOCKS + (VBH_MC_STATIC_MAX_BLOCKS + kChunk - 1) / kChunk + 1;
+__device__ __align__(256) int64_t scratch[kStaticWork];
+
+// Device address of `scratch` on the current device, looked up once per device.
+int static_work(int64_t **out) {
+    static std::mutex mu;
+    static std::vector<std::pair<int, int64_t *>> addr;
+    int dev = 0;
+    VBH_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
+    for (const auto &a : addr)
+        if (a.first == dev) {
+            *out = a.second;
+            return VBH_OK;
+        }
+    void *p = nullptr;
+    VBH_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return VBH_EHIP;
+    addr.emplace_back(dev, static_cast<int64_t *>(p));
+    *out = static_cast<int64_t *>(p);
+    return VBH_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int vbh_mc_triangulate_static(const int32_t *d_keys, const uint32_t *d_mcv, int64_t n, float voxel_size,
+                              float *d_pos, uint8_t *d_rgb, int64_t cap, int64_t *h_count, void *stream) {
+    if (n < 0 || n > VBH_MC_STATIC_MAX_BLOCKS) return VBH_EINVAL;
+    int64_t *work = nullptr;
+    if (int rc = static_work(&work)) return rc;
+    return vbh_mc_triangulate(d_keys, d_mcv, n, voxel_size, d_pos, d_rgb, cap, work, h_count, stream);
+}
+
 int vbh_mc_triangulate(const int32_t *d_keys, const uint32_t *d_mcv, int64_t n, float voxel_size, float *d_pos,
                        uint8_t *d_rgb, int64_t cap, int64_t *d_work, int64_t *h_count, void *stream) {
     if (n < 0 || cap < 0 || !(voxel_size > 0.0f) || (n > 0 && (!d_keys || !d_mcv || !d_work)) ||
