@@ -31,6 +31,7 @@ def _signatures():
         "orc_map_export": ([vp, i32p, i32p, i64], i64),
         "orc_scene_new": ([vp], vp), "orc_scene_free": ([vp], None),
         "orc_integrate_frame": ([vp, f32p, u8p, f32p, C.c_uint32], C.c_int),
+        "orc_integrate_blocks": ([vp, i32p, i64, f32p, u8p, f32p, C.c_uint32], C.c_int),
         "orc_last_touched": ([vp, i32p, i64], i64),
         "orc_last_new": ([vp, i32p, i64], i64),
         "orc_last_mc_updated": ([vp, i32p, i64], i64),
@@ -177,6 +178,13 @@ class Scene:
         c = None if rgb is None else np.ascontiguousarray(rgb, np.uint8)
         P = pose32(pose)
         return self.L.orc_integrate_frame(self.h, _p(d), _p(c), _p(P), frame_id)
+
+    def integrate_blocks(self, keys, depth, rgb, pose, frame_id: int) -> int:
+        k, n = _keys(keys)
+        d = np.ascontiguousarray(depth, np.float32)
+        c = None if rgb is None else np.ascontiguousarray(rgb, np.uint8)
+        P = pose32(pose)
+        return int(self.L.orc_integrate_blocks(self.h, _p(k) if n else None, n, _p(d), _p(c), _p(P), frame_id))
 
     def _keylist(self, fn):
         n = fn(self.h, None, 0)

@@ -420,6 +420,40 @@ int orc_integrate_frame(void *s, const float *depth, const uint8_t *rgb, const f
     return S.error;
 }
 
+int orc_integrate_blocks(void *s, const int32_t *keys, int64_t n, const float *depth, const uint8_t *rgb,
+                         const float *P, uint32_t frame_id) {
+    Scene &S = *static_cast<Scene *>(s);
+    if (n < 0 || (n > 0 && !keys) || !depth || !P || frame_id == 0 || frame_id <= S.last_frame) return ORC_EINVAL;
+    S.last_frame = frame_id;
+    // the listed blocks replace the band blocks as the touched set
+    std::vector<uint64_t> touched;
+    for (int64_t i = 0; i < n; ++i) {
+        const int32_t *k = keys + 3 * i;
+        if (!key_in_range(k[0], k[1], k[2])) {
+            S.error = ORC_EINVAL;
+            continue;
+        }
+        touched.push_back(pack(k[0], k[1], k[2]));
+    }
+    std::sort(touched.begin(), touched.end());
+    touched.erase(std::unique(touched.begin(), touched.end()), touched.end());
+    S.last_new.clear();
+    std::vector<uint64_t> with_storage;
+    for (uint64_t k : touched) {
+        if (!S.get(k)) {
+            if (!S.alloc(k)) continue;
+            S.last_new.push_back(k);
+        }
+        with_storage.push_back(k);
+    }
+    S.last_touched = with_storage;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < int64_t(with_storage.size()); ++i)
+        integrate_block(*S.get(with_storage[size_t(i)]), with_storage[size_t(i)], S.p, depth, rgb, P);
+    mc_update(S, with_storage, frame_id);
+    return S.error;
+}
+
 int64_t orc_last_touched(void *s, int32_t *keys, int64_t cap) {
     return write_keys(static_cast<Scene *>(s)->last_touched, keys, cap);
 }

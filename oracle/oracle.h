@@ -58,6 +58,11 @@ void orc_scene_free(void *s);
  * NULL; pose_c2w float32 row-major 3x4; frame_id strictly increasing and > 0. */
 int orc_integrate_frame(void *s, const float *depth, const uint8_t *rgb, const float *pose_c2w,
                         uint32_t frame_id);
+/* The same fusion with the allocation step replaced by a list of n block keys
+ * (duplicates allowed; absent blocks are allocated; keys out of range record ORC_EINVAL):
+ * the listed blocks are the touched set, integrated and MC-updated as update frame_id. */
+int orc_integrate_blocks(void *s, const int32_t *keys, int64_t n, const float *depth, const uint8_t *rgb,
+                         const float *pose_c2w, uint32_t frame_id);
 /* Keys of the last frame's touched / newly allocated / MC-updated blocks (sorted). */
 int64_t orc_last_touched(void *s, int32_t *keys, int64_t cap);
 int64_t orc_last_new(void *s, int32_t *keys, int64_t cap);
