@@ -389,11 +389,72 @@ def diff_bench(vbh, reps=5):
             "backward_ms_per_frame": bwd / n, "backward_over_forward": bwd / fwd, "loss": float(loss)}
 
 
-def serve_bench(vbh, seconds=60.0, warmup=10.0, clients=64, rate=30.0, n_unique_frames=600):
+def large_batch_bench(vbh, vs=0.003, wall=3.9):
+    """Integration and MC extraction of more than a million blocks in one launch each,
+    beyond the 256 MB Infinity Cache: every block of a 3 mm volume (2.4 cm blocks) whose
+    centre lies in the 640x480 camera's frustum between 0.45 m and wall - 5 cm, in front of
+    a fronto-parallel wall at `wall` metres (every voxel that projects into the image is
+    in free space, so it is read and written).  The list is integrated twice (the first
+    pass allocates the blocks); the second pass is the one measured, with kernel start and
+    stop events attached to its dispatches."""
+    import torch
+    from datagen import configs
+    cam = configs.FULL_CAM
+    bs = 8 * vs
+    vol = configs.Volume(slots=1 << 23, pool_blocks=1 << 21, voxel_size=vs, trunc=4 * vs, depth_min=0.4,
+                         depth_max=4.0, log_capacity=1 << 23)
+    zs = torch.arange(int(0.45 / bs), int((wall - 0.05) / bs), device="cuda", dtype=torch.int64)
+    zc = (zs.to(torch.float64) + 0.5) * bs
+    keys = []
+    for z, c in zip(zs.tolist(), zc.tolist()):
+        hx = c * (cam.width / 2) / cam.fx
+        hy = c * (cam.height / 2) / cam.fy
+        xs = torch.arange(int(-hx / bs) - 1, int(hx / bs) + 1, device="cuda")
+        ys = torch.arange(int(-hy / bs) - 1, int(hy / bs) + 1, device="cuda")
+        xc, yc = (xs.to(torch.float64) + 0.5) * bs, (ys.to(torch.float64) + 0.5) * bs
+        xs, ys = xs[xc.abs() <= hx], ys[yc.abs() <= hy]
+        g = torch.stack(torch.meshgrid(xs, ys, indexing="ij"), -1).reshape(-1, 2)
+        keys.append(torch.cat([g, torch.full((g.shape[0], 1), z, device="cuda")], 1))
+    keys = torch.cat(keys).to(torch.int32).contiguous()
+    depth = torch.full((cam.height, cam.width), wall, dtype=torch.float32, device="cuda")
+    rgb = torch.full((cam.height, cam.width, 3), 128, dtype=torch.uint8, device="cuda")
+    pose = [[1.0, 0, 0, 0], [0, 1.0, 0, 0], [0, 0, 1.0, 0]]
+    S = vbh.Scene(vbh.make_params(vol, cam))
+    S.vbh_integrate_blocks(keys, depth, rgb, pose, 1)
+    torch.cuda.synchronize()
+    S.vbh_scene_enable_timing(1)
+    S.vbh_scene_timing()  # discard the first pass
+    S.vbh_integrate_blocks(keys, depth, rgb, pose, 2)
+    ms, n_timed = S.vbh_scene_timing()
+    st = S.vbh_scene_stats()
+    if S.vbh_scene_status() != 0:
+        raise RuntimeError("large-batch scene reported an error")
+    out = {"workload": f"{keys.shape[0]} blocks of a {vs * 1e3:g} mm volume in the 640x480 frustum in front of a "
+                       f"wall at {wall} m, integrated (second pass) and MC-extracted in one launch each",
+           "blocks": int(st["n_touched"]), "mc_blocks": int(st["n_mc"]),
+           "voxel_updates": int(st["n_voxel_updates"])}
+    for stage, nbytes in (("integrate", INT_BYTES_PER_BLOCK * st["n_touched"] + INT_BYTES_PER_PIXEL * cam.width * cam.height),
+                          ("mc_extract", MC_BYTES_PER_BLOCK * st["n_mc"])):
+        t = ms[stage] / max(n_timed, 1)
+        gbs = nbytes / (t * 1e-3) / 1e9
+        out[stage] = {"kernel_ms": t, "algorithmic_bytes": float(nbytes), "achieved": gbs, "peak": HBM_PEAK_GBS,
+                      "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
+    S.close()
+    del keys, depth, rgb
+    torch.cuda.empty_cache()
+    return out
+
+
+SERVE_MODES = {0: "rounds", 1: "persistent"}
+
+
+def serve_bench(vbh, seconds=60.0, warmup=10.0, clients=64, rate=30.0, n_unique_frames=600, mode=0):
     """Serving: ~2M-block scene resident on the device, `clients` clients with Poisson
     arrivals (`rate` req/s each), request sizes floor(10^U(2,5)) blocks, every client
     starting from cursor 0, while 640x480 frames are fused at 30 Hz.  Latency = arrival to
-    results in device memory; statistics over requests arriving after the warm-up."""
+    results in device memory; statistics over requests arriving after the warm-up.
+    mode: 0 rounds of kernels on 4 streams, 1 one persistent launch per scene version
+    (4 teams)."""
     import numpy as np
     import torch
     from datagen import configs
@@ -424,7 +485,8 @@ def serve_bench(vbh, seconds=60.0, warmup=10.0, clients=64, rate=30.0, n_unique_
     order = np.argsort(arr, kind="stable")
     arr, cl = arr[order], cl[order]
     lim = np.floor(10 ** rng.uniform(2, 5, arr.size)).astype(np.int64)
-    srv = vbh.Server(S, arena_bytes=24 << 30, max_inflight=512, n_streams=4, n_clients=clients, max_batch=64)
+    srv = vbh.Server(S, arena_bytes=24 << 30, max_inflight=512, n_streams=4, n_clients=clients, max_batch=64,
+                     mode=mode)
     log(f"[bench] serving {arr.size} requests over {total:.0f}s with {nf} fused frames")
     res = srv.vbh_server_run(cl, lim, arr, frames=frames)
     if (res["status"] != 0).any() or S.vbh_scene_status() != 0:
@@ -434,7 +496,8 @@ def serve_bench(vbh, seconds=60.0, warmup=10.0, clients=64, rate=30.0, n_unique_
     queue = (res["admit_s"] - res["arrival_s"])[m] * 1e3
     blocks = res["count"][m].sum()
     span = res["done_s"][m].max() - warmup
-    out = {"requests": int(m.sum()), "clients": clients, "rate_per_client": rate, "seconds": seconds,
+    out = {"mode": SERVE_MODES[mode], "requests": int(m.sum()), "clients": clients, "rate_per_client": rate,
+           "seconds": seconds,
            "scene_blocks": int(st["n_blocks"]), "frames_fused": nf,
            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
            "p50_queue_ms": float(np.percentile(queue, 50)), "p99_queue_ms": float(np.percentile(queue, 99)),
@@ -488,7 +551,12 @@ def main():
     ap.add_argument("--no-client", action="store_true")
     ap.add_argument("--no-h2d", action="store_true")
     ap.add_argument("--no-per-frame", action="store_true")
+    ap.add_argument("--no-large", action="store_true", help="skip the large-batch integration/extraction run")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
+    ap.add_argument("--serve-mode", type=int, default=0, choices=[0, 1],
+                    help="serving form of the headline serve run: 0 rounds of kernels, 1 persistent launch")
+    ap.add_argument("--serve-ab-seconds", type=float, default=20.0,
+                    help="length of the A/B run of the other serving form (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--timing-period", type=int, default=0,
                     help="attach kernel start/stop events to every n-th frame of the timed run "
@@ -563,6 +631,11 @@ def main():
                   "mc_blocks_per_frame": stats["total_mc"] / K,
                   "voxel_updates_per_frame": stats["total_voxel_updates"] / K},
     }
+    if not args.no_large:
+        log("[bench] large-batch integration and extraction")
+        lb = large_batch_bench(vbh)
+        result["roofline"]["large_batch"] = lb
+        log(f"[bench] large batch: {lb}")
     if not args.no_client:
         log("[bench] client triangulation and scene reset on the fused scene")
         result["client"] = client_bench(vbh, S, traj[K - 1], K + 1)
@@ -589,8 +662,11 @@ def main():
         log(f"[bench] diff: {result['diff']}")
     if not args.no_serve:
         log("[bench] serving")
-        result["serve"] = serve_bench(vbh, seconds=args.serve_seconds)
+        result["serve"] = serve_bench(vbh, seconds=args.serve_seconds, mode=args.serve_mode)
         log(f"[bench] serve: {result['serve']}")
+        if args.serve_ab_seconds > 0:
+            result["serve_ab"] = serve_bench(vbh, seconds=args.serve_ab_seconds, mode=1 - args.serve_mode)
+            log(f"[bench] serve A/B: {result['serve_ab']}")
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
         d2, c2, t2 = stage_frames(200, "cuda")

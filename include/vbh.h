@@ -180,6 +180,15 @@ void vbh_scene_destroy(vbh_scene *s);
 int vbh_integrate_frame(vbh_scene *s, const float *d_depth, const uint8_t *d_rgb, const float *pose_c2w,
                         uint32_t frame_id, void *stream);
 
+/* Integration of one frame into an explicit list of blocks instead of the band blocks
+ * (Sec. 4.1 fusion with the allocation step replaced by the list): the n keys (duplicates
+ * allowed; absent blocks are allocated, keys out of range record VBH_EINVAL) form the
+ * touched set, every voxel of them is integrated with the rules of vbh_integrate_frame
+ * (step 2), and the MC update (step 3) follows, as update frame_id.  For batches larger
+ * than a frame's band, e.g. every block in front of a surface. */
+int vbh_integrate_blocks(vbh_scene *s, const int32_t *d_keys, int64_t n, const float *d_depth, const uint8_t *d_rgb,
+                         const float *pose_c2w, uint32_t frame_id, void *stream);
+
 /* Fuse n consecutive frames, each exactly as vbh_integrate_frame would, in order: d_depth
  * float32 [n][H*W], d_rgb uint8 [n][H*W*3] or NULL, poses_c2w a HOST array of n*12 floats
  * (copied), frame ids first_frame_id .. first_frame_id + n - 1 (first_frame_id > 0 and
@@ -319,23 +328,35 @@ int vbh_scene_timing(vbh_scene *s, double *ms_out, int64_t *h_frames, int64_t *h
  * cursor 0 and so receives every block.
  * vbh_server_run replays a request schedule in real time: a request is admitted when its
  * arrival time has passed, its client has no request in flight, a request slot is free
- * and its result fits in the device arena; admitted requests are launched in rounds on a
- * pool of streams, overlapping with earlier rounds.  Frames given to it are fused at their
- * times on another stream; a frame's MC update waits until the requests in flight have
- * completed and no request is launched while it runs, so every request is served against
- * one scene version (result identical to running it alone at that version).
+ * and its result fits in the device arena.  VBH_SERVE_ROUNDS: admitted requests are
+ * launched in rounds of four kernels on a pool of streams, overlapping with earlier
+ * rounds; frames given to the run are fused at their times on another stream, and a
+ * frame's MC update waits until the requests in flight have completed while no request is
+ * launched.  VBH_SERVE_PERSISTENT: admitted requests are published in batches to a ring in
+ * pinned host memory, drained by one persistent launch whose teams of workgroups serve
+ * batches concurrently (results written straight into the requests' output buffers when
+ * given); a frame that falls due stops the launch after its published batches, is fused
+ * with its MC update, and a new launch serves the next version.  Either way every request
+ * is served against one scene version (result identical to running it alone at that
+ * version).  A persistent launch that waits longer than its bounds (10 s for work, 5 s
+ * for a step) leaves, and the run returns VBH_EHIP.
  * While a server runs, the scene must not be used through other entry points.  Between
  * runs it may be (frames fused, blocks written or reset): each run starts from the
  * scene's state at its entry, so such updates must have completed by then (for example,
  * the caller synchronised the stream it issued them on). */
 typedef struct vbh_server vbh_server;
 
+#define VBH_SERVE_ROUNDS 0     /* each batch is a round of four kernels on a pool of streams */
+#define VBH_SERVE_PERSISTENT 1 /* one persistent launch per scene version drains a ring of batches */
 typedef struct vbh_server_config {
     int64_t arena_bytes; /* device memory for results in flight, >= 4096 */
     int32_t max_inflight; /* request slots, 1..4096 */
-    int32_t n_streams;   /* serving streams, 1..8 (default priority) */
+    int32_t n_streams;   /* rounds: serving streams, 1..8 (default priority); persistent: teams
+                            of workgroups, 1..4, each serving one batch at a time */
     int32_t n_clients;   /* client table size, >= 1 */
-    int32_t max_batch;   /* requests per launch round, 1..256 */
+    int32_t max_batch;   /* requests per round or batch, 1..256 */
+    int32_t mode;        /* VBH_SERVE_ROUNDS or VBH_SERVE_PERSISTENT */
+    int32_t workgroups;  /* persistent launch size, 0..4096 (0: two per compute unit) */
 } vbh_server_config;
 
 typedef struct vbh_request {

@@ -53,7 +53,7 @@ class vbh_stats(C.Structure):
 
 class vbh_server_config(C.Structure):
     _fields_ = [("arena_bytes", C.c_int64), ("max_inflight", C.c_int32), ("n_streams", C.c_int32),
-                ("n_clients", C.c_int32), ("max_batch", C.c_int32)]
+                ("n_clients", C.c_int32), ("max_batch", C.c_int32), ("mode", C.c_int32), ("workgroups", C.c_int32)]
 
 
 class vbh_request(C.Structure):
@@ -91,6 +91,7 @@ SIGNATURES = {
     "vbh_scene_create": ([C.POINTER(vbh_params), C.POINTER(_V)], C.c_int),
     "vbh_scene_destroy": ([_V], None),
     "vbh_integrate_frame": ([_V, _P, _P, C.POINTER(C.c_float), C.c_uint32, _V], C.c_int),
+    "vbh_integrate_blocks": ([_V, _P, _I64, _P, _P, C.POINTER(C.c_float), C.c_uint32, _V], C.c_int),
     "vbh_integrate_frames": ([_V, _P, _P, C.POINTER(C.c_float), C.c_uint32, _I64, _V], C.c_int),
     "vbh_integrate_frames_host": ([_V, _P, _P, C.POINTER(C.c_float), C.c_uint32, _I64, _V], C.c_int),
     "vbh_extract_mc_indices": ([_V, _P, _I64, _P, _P, _V], C.c_int),
@@ -335,6 +336,16 @@ class Scene:
                                          _ptr(rgb, torch.uint8, 3 * n, "rgb"), pose, frame_id, _stream()),
                "vbh_integrate_frame")
 
+    def vbh_integrate_blocks(self, keys, depth, rgb, pose_c2w, frame_id: int):
+        kp, nk = _keys(keys)
+        p = self.params
+        n = p.width * p.height
+        P = _poses_f32(pose_c2w, 1)
+        _check(lib().vbh_integrate_blocks(self.h, kp, nk, _ptr(depth, torch.float32, n, "depth"),
+                                          _ptr(rgb, torch.uint8, 3 * n, "rgb"), P.ctypes.data_as(C.POINTER(C.c_float)),
+                                          frame_id, _stream()),
+               "vbh_integrate_blocks")
+
     def vbh_integrate_frames(self, depth, rgb, poses_c2w, first_frame_id: int):
         """Fuse frames depth[i] (rgb[i], poses_c2w[i]) as ids first_frame_id + i."""
         p = self.params
@@ -463,8 +474,10 @@ class Server:
     """Serving loop over a scene (vbh_server_*)."""
 
     def __init__(self, scene: Scene, arena_bytes: int, max_inflight: int = 256, n_streams: int = 4,
-                 n_clients: int = 64, max_batch: int = 64):
-        self.cfg = vbh_server_config(arena_bytes, max_inflight, n_streams, n_clients, max_batch)
+                 n_clients: int = 64, max_batch: int = 64, mode: int = 0, workgroups: int = 0):
+        """mode 0: rounds of kernels on n_streams streams; mode 1: one persistent launch per
+        scene version with n_streams teams (1..4) of `workgroups` workgroups in all."""
+        self.cfg = vbh_server_config(arena_bytes, max_inflight, n_streams, n_clients, max_batch, mode, workgroups)
         self._L = lib()
         h = C.c_void_p()
         _check(lib().vbh_server_create(scene.h, C.byref(self.cfg), C.byref(h)), "vbh_server_create")

@@ -773,6 +773,17 @@ __global__ void __launch_bounds__(kBlock) k_load_claim(Dev S, const int32_t *key
     }
 }
 
+// Thread per pixel: the pixel records integration gathers (depth bits, colour), for
+// updates whose blocks are not found by the allocation kernel.
+__global__ void __launch_bounds__(kBlock) k_pix_pack(Dev S, int64_t hw, const float *__restrict__ depth,
+                                                     const uint8_t *__restrict__ rgb) {
+    for (int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x; p < hw; p += int64_t(gridDim.x) * kBlock) {
+        uint32_t c = 0u;
+        if (rgb) c = uint32_t(rgb[3 * p]) | uint32_t(rgb[3 * p + 1]) << 8 | uint32_t(rgb[3 * p + 2]) << 16;
+        S.PIX[p] = make_uint2(__float_as_uint(depth[p]), c);
+    }
+}
+
 __global__ void __launch_bounds__(kBlock) k_load_copy(Dev S, const int32_t *keys, int64_t n, const float *F,
                                                       const uint8_t *W, const uint8_t *rgb) {
     const int lane = lane_id();
@@ -1074,11 +1085,41 @@ unsigned wave_grid(const vbh_scene *s, int64_t cap_items) {
     return unsigned(need < want ? (need > 0 ? need : 1) : want);
 }
 
+// Start/stop events for the kernels of update seq if it is one of the timed updates.
+StageTimer *timer_for(vbh_scene *s, int seq) {
+    if (s->timing_period <= 0 || seq % s->timing_period != 0) return nullptr;
+    if (s->ev_free.empty()) {
+        StageTimer t;
+        for (auto &e : t.ev)
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        s->ev_free.push_back(t);
+    }
+    s->ev_pending.push_back(s->ev_free.back());
+    s->ev_free.pop_back();
+    StageTimer *tm = &s->ev_pending.back();
+    tm->ran = 0;
+    return tm;
+}
+
+// Launches a kernel; a timed one gets start/stop events attached to its dispatch (no
+// extra packets between the kernels).
+template <typename... Args, typename F>
+void launch(StageTimer *tm, int stage, hipStream_t st, F kern, dim3 grid, dim3 block, Args... args) {
+    if (tm) {
+        tm->ran |= 1u << stage;
+        hipExtLaunchKernelGGL(kern, grid, block, 0, st, tm->ev[2 * stage], tm->ev[2 * stage + 1], 0, args...);
+    } else {
+        hipLaunchKernelGGL(kern, grid, block, 0, st, args...);
+    }
+}
+
 // Runs the MC update for the blocks in the touched list of update `seq`.
-int mc_update(vbh_scene *s, uint32_t frame, int seq, hipStream_t st) {
+// n_partials: workgroups of the update's integration kernel whose statistics the
+// extraction kernel reduces (0 if none ran).
+int mc_update(vbh_scene *s, uint32_t frame, int seq, hipStream_t st, StageTimer *tm = nullptr, int n_partials = 0) {
     const unsigned g = unsigned(s->cus) * 8;
-    k_mc_mark<<<unsigned(s->cus) * 2, kMarkThreads, 0, st>>>(s->d, frame, seq);
-    k_mc_extract<<<g, kBlock, 0, st>>>(s->d, seq, 0, frame);
+    launch(tm, 2, st, k_mc_mark, dim3(unsigned(s->cus) * 2), dim3(kMarkThreads), s->d, frame, seq);
+    launch(tm, 3, st, k_mc_extract, dim3(g), dim3(kBlock), s->d, seq, n_partials, frame);
     VBH_LAUNCHED();
     return VBH_OK;
 }
@@ -1132,34 +1173,6 @@ Frame make_frame(const vbh_scene *s, const float *pose) {
 }  // namespace vbh
 
 namespace {
-// Start/stop events for the kernels of update seq if it is one of the timed updates.
-StageTimer *timer_for(vbh_scene *s, int seq) {
-    if (s->timing_period <= 0 || seq % s->timing_period != 0) return nullptr;
-    if (s->ev_free.empty()) {
-        StageTimer t;
-        for (auto &e : t.ev)
-            if (hipEventCreate(&e) != hipSuccess) return nullptr;
-        s->ev_free.push_back(t);
-    }
-    s->ev_pending.push_back(s->ev_free.back());
-    s->ev_free.pop_back();
-    StageTimer *tm = &s->ev_pending.back();
-    tm->ran = 0;
-    return tm;
-}
-
-// Launches a kernel; a timed one gets start/stop events attached to its dispatch (no
-// extra packets between the kernels).
-template <typename... Args, typename F>
-void launch(StageTimer *tm, int stage, hipStream_t st, F kern, dim3 grid, dim3 block, Args... args) {
-    if (tm) {
-        tm->ran |= 1u << stage;
-        hipExtLaunchKernelGGL(kern, grid, block, 0, st, tm->ev[2 * stage], tm->ev[2 * stage + 1], 0, args...);
-    } else {
-        hipLaunchKernelGGL(kern, grid, block, 0, st, args...);
-    }
-}
-
 dim3 alloc_grid(const vbh_scene *s) { return dim3(unsigned((s->p.width + 31) / 32), unsigned((s->p.height + 15) / 16)); }
 }  // namespace
 
@@ -1350,6 +1363,28 @@ int vbh_integrate_frame(vbh_scene *s, const float *d_depth, const uint8_t *d_rgb
     for (int i = 0; i < 12; ++i)
         if (!std::isfinite(pose_c2w[i])) return VBH_EINVAL;
     return vbh::scene_fuse(s, d_depth, d_rgb, pose_c2w, frame_id, true, as_stream(stream));
+}
+
+int vbh_integrate_blocks(vbh_scene *s, const int32_t *d_keys, int64_t n, const float *d_depth, const uint8_t *d_rgb,
+                         const float *pose_c2w, uint32_t frame_id, void *stream) {
+    if (!s || n < 0 || (n > 0 && !d_keys) || !d_depth || !pose_c2w || frame_id == 0 || frame_id <= s->last_frame)
+        return VBH_EINVAL;
+    for (int i = 0; i < 12; ++i)
+        if (!std::isfinite(pose_c2w[i])) return VBH_EINVAL;
+    hipStream_t st = as_stream(stream);
+    const Frame fr = make_frame(s, pose_c2w);
+    const int seq = s->seq;
+    StageTimer *tm = timer_for(s, seq);
+    const unsigned g = unsigned(s->cus) * 8;
+    const int64_t hw = int64_t(s->p.width) * s->p.height;
+    k_load_claim<<<grid_for(n, kBlock, 8192), kBlock, 0, st>>>(s->d, d_keys, n, frame_id, seq);
+    k_pix_pack<<<grid_for(hw, kBlock, 4096), kBlock, 0, st>>>(s->d, hw, d_depth, d_rgb);
+    VBH_LAUNCHED();
+    launch(tm, 1, st, k_integrate, dim3(g), dim3(kBlock), s->d, fr, int(d_rgb != nullptr), seq, 0);
+    if (int rc = mc_update(s, frame_id, seq, st, tm, int(g))) return rc;
+    s->seq = seq + 1;
+    s->last_frame = frame_id;
+    return VBH_OK;
 }
 
 int vbh_integrate_frames(vbh_scene *s, const float *d_depth, const uint8_t *d_rgb, const float *poses_c2w,

@@ -30,6 +30,7 @@
 #include <thread>
 #include <vector>
 
+#include "arena.hpp"
 #include "scene.hpp"
 
 using namespace vbh;
@@ -53,6 +54,8 @@ struct SvReq {
     int64_t off_keys;    // int32 [limit][3]
     int64_t off_mc;      // uint32 [limit][512]
     int64_t off_meta;    // int64 count, uint64 next cursor
+    int32_t *keys_out;   // persistent form: the caller's result buffers (written directly;
+    uint32_t *mc_out;    // NULL: the arena slices above)
 };
 
 struct SvRound {
@@ -79,9 +82,11 @@ __device__ __forceinline__ bool entry_live(const Dev &S, uint64_t pos, uint64_t 
     return S.mc_stamp[uint32_t(e)] == uint32_t(e >> 32);
 }
 
-__global__ void __launch_bounds__(kSvWG) k_sv_count(Dev S, SvRound R) {
+// The four steps of a round, for workgroup wg of G (a kernel's grid, or the workgroups of
+// the persistent launch).
+__device__ __forceinline__ void sv_count(const Dev &S, const SvRound &R, int64_t wg, int64_t G) {
     __shared__ int part[kSvWG / 64];
-    for (int64_t it = blockIdx.x; it < R.total_chunks; it += gridDim.x) {
+    for (int64_t it = wg; it < R.total_chunks; it += G) {
         const int r = find_req(R, it, true);
         const SvReq q = R.req[r];
         const int64_t c = it - q.chunk_base;
@@ -102,9 +107,9 @@ __global__ void __launch_bounds__(kSvWG) k_sv_count(Dev S, SvRound R) {
 
 // One workgroup per request: exclusive scan of its chunk counts, count and (when fewer
 // than `limit` live entries exist) the next cursor.
-__global__ void __launch_bounds__(kSvWG) k_sv_scan(SvRound R) {
+__device__ __forceinline__ void sv_scan_one(const SvRound &R, int r) {
     __shared__ int64_t part[kSvWG];
-    const SvReq q = R.req[blockIdx.x];
+    const SvReq q = R.req[r];
     int64_t *cnt = reinterpret_cast<int64_t *>(R.arena + q.off_cnt);
     const int64_t per = (q.n_chunks + kSvWG - 1) / kSvWG;
     const int64_t lo = threadIdx.x * per, hi = lo + per < q.n_chunks ? lo + per : q.n_chunks;
@@ -133,10 +138,10 @@ __global__ void __launch_bounds__(kSvWG) k_sv_scan(SvRound R) {
     }
 }
 
-__global__ void __launch_bounds__(kSvWG) k_sv_emit(Dev S, SvRound R) {
+__device__ __forceinline__ void sv_emit(const Dev &S, const SvRound &R, int64_t wg, int64_t G) {
     __shared__ int wc[kSvWG / 64];
     const int lane = lane_id(), wave = threadIdx.x >> 6;
-    for (int64_t it = blockIdx.x; it < R.total_chunks; it += gridDim.x) {
+    for (int64_t it = wg; it < R.total_chunks; it += G) {
         const int r = find_req(R, it, true);
         const SvReq q = R.req[r];
         const int64_t c = it - q.chunk_base;
@@ -166,11 +171,12 @@ __global__ void __launch_bounds__(kSvWG) k_sv_emit(Dev S, SvRound R) {
     }
 }
 
-// One wave per selected block: its key and 512 MC voxels into the arena.
-__global__ void __launch_bounds__(kSvWG) k_sv_gather(Dev S, SvRound R) {
+// One wave per selected block: its key and 512 MC voxels into the arena (or the caller's
+// buffers).
+__device__ __forceinline__ void sv_gather(const Dev &S, const SvRound &R, int64_t wg, int64_t G) {
     const int lane = lane_id();
-    const int64_t gw = int64_t(blockIdx.x) * (kSvWG / 64) + (threadIdx.x >> 6);
-    const int64_t nw = int64_t(gridDim.x) * (kSvWG / 64);
+    const int64_t gw = wg * (kSvWG / 64) + (threadIdx.x >> 6);
+    const int64_t nw = G * (kSvWG / 64);
     for (int64_t it = gw; it < R.total_items; it += nw) {
         const int r = find_req(R, it, false);
         const SvReq q = R.req[r];
@@ -179,15 +185,188 @@ __global__ void __launch_bounds__(kSvWG) k_sv_gather(Dev S, SvRound R) {
         if (b >= count) continue;
         const int32_t pool = reinterpret_cast<const int32_t *>(R.arena + q.off_sel)[b];
         const uint4 *src = reinterpret_cast<const uint4 *>(S.MCV + int64_t(pool) * 512);
-        uint4 *dst = reinterpret_cast<uint4 *>(R.arena + q.off_mc) + b * 128;
+        uint4 *dst = reinterpret_cast<uint4 *>(q.mc_out ? reinterpret_cast<char *>(q.mc_out) : R.arena + q.off_mc) +
+                     b * 128;
         dst[lane] = src[lane];
         dst[lane + 64] = src[lane + 64];
         if (lane < 3) {
             int32_t k[3];
             unpack_key(S.pool_key[pool], k[0], k[1], k[2]);
-            reinterpret_cast<int32_t *>(R.arena + q.off_keys)[b * 3 + lane] = k[lane];
+            int32_t *kd = q.keys_out ? q.keys_out : reinterpret_cast<int32_t *>(R.arena + q.off_keys);
+            kd[b * 3 + lane] = k[lane];
         }
     }
+}
+
+__global__ void __launch_bounds__(kSvWG) k_sv_count(Dev S, SvRound R) { sv_count(S, R, blockIdx.x, gridDim.x); }
+__global__ void __launch_bounds__(kSvWG) k_sv_scan(SvRound R) { sv_scan_one(R, int(blockIdx.x)); }
+__global__ void __launch_bounds__(kSvWG) k_sv_emit(Dev S, SvRound R) { sv_emit(S, R, blockIdx.x, gridDim.x); }
+__global__ void __launch_bounds__(kSvWG) k_sv_gather(Dev S, SvRound R) { sv_gather(S, R, blockIdx.x, gridDim.x); }
+
+// ----------------------------------------------------------------- persistent form
+// One launch serves batches of admitted requests from a ring in pinned host memory until
+// the host asks it to stop.  Its workgroups form `teams`; team t takes batches t, t +
+// teams, ..., so a batch admitted while another is on the device starts at once on a free
+// team.  Within a batch a team runs the four steps of a round, separated by barriers among
+// the team's workgroups (all of them resident: the grid is sized to fit the device).  The
+// team's first workgroup waits for the batch to be published, copies its descriptors to
+// device memory, and after the last step writes each request's count and next cursor and
+// the batch's completion word to host memory.  Every wait is bounded in time: a wait that
+// expires raises the abort word, and all workgroups leave.
+constexpr int kPRing = 8;      // batch slots of the ring
+constexpr int kMaxTeams = 4;
+
+struct PBatch {
+    int32_t n;  // requests
+    int32_t pad;
+    int64_t total_chunks, total_items;
+    SvReq req[kMaxBatch];
+};
+
+// Shared with the host (pinned, coherent, mapped).
+struct PHost {
+    unsigned long long published;  // batches published in this launch (host)
+    unsigned long long stop;       // host: leave once every published batch is done
+    unsigned long long err;        // device: a wait expired
+    unsigned long long pad;
+    unsigned long long done[kPRing];  // batch sequence number + 1, once complete (device)
+    int64_t meta[kPRing][kMaxBatch][2];  // count and next cursor per request (device)
+    PBatch batch[kPRing];                 // descriptors (host)
+};
+
+struct PTeam {
+    unsigned int count, gen;  // team barrier
+    unsigned int exit, pad;
+    PBatch cur;               // the batch being served, copied from host memory
+};
+
+struct PDev {
+    unsigned int abort;
+    unsigned int pad[63];
+    PTeam team[kMaxTeams];
+};
+
+__device__ __forceinline__ unsigned long long ld_sys(const unsigned long long *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ unsigned int ld_dev(const unsigned int *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Barrier of the team's G workgroups; false if the abort word was raised or the wait took
+// longer than `ticks` of the constant wall clock (then this workgroup raises it).
+// Every wave releases its own writes before the arrival (a workgroup barrier does not wait
+// for other waves' stores) and acquires after it.
+__device__ bool team_sync(PDev *P, PTeam &T, unsigned int G, long long ticks) {
+    __shared__ int ok;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ok = 1;
+        const unsigned int g = ld_dev(&T.gen);
+        if (atomicAdd(&T.count, 1u) == G - 1) {
+            __hip_atomic_store(&T.count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __threadfence();
+            atomicAdd(&T.gen, 1u);
+        } else {
+            const long long t0 = wall_clock64();
+            while (ld_dev(&T.gen) == g) {
+                if (ld_dev(&P->abort) || wall_clock64() - t0 > ticks) {
+                    atomicOr(&P->abort, 1u);
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        if (ld_dev(&P->abort)) ok = 0;
+    }
+    __syncthreads();
+    __threadfence();  // the other workgroups' writes are visible after the barrier
+    return ok != 0;
+}
+
+__global__ void __launch_bounds__(kSvWG) k_sv_pinit(PDev *P) {
+    for (int i = threadIdx.x; i < kMaxTeams; i += blockDim.x) {
+        P->team[i].count = 0;
+        P->team[i].gen = 0;
+        P->team[i].exit = 0;
+    }
+    if (threadIdx.x == 0) P->abort = 0;
+}
+
+__global__ void __launch_bounds__(kSvWG) k_sv_persistent(Dev S, PHost *H, PDev *P, char *arena, int teams,
+                                                         long long ticks_idle, long long ticks_step) {
+    const int team = int(blockIdx.x) % teams;
+    const unsigned int wg = blockIdx.x / unsigned(teams);
+    const unsigned int G = (gridDim.x - unsigned(team) + unsigned(teams) - 1) / unsigned(teams);
+    PTeam &T = P->team[team];
+    __shared__ int state;  // 0 serve, 1 stop, 2 expired
+    for (unsigned long long b = unsigned(team);; b += unsigned(teams)) {
+        const int slot = int(b % kPRing);
+        if (wg == 0) {
+            if (threadIdx.x == 0) {
+                int st = 0;
+                const long long t0 = wall_clock64();
+                while (ld_sys(&H->published) <= b) {
+                    if (ld_sys(&H->stop)) {
+                        // the host raises stop after its last publication: a second read of
+                        // the count after seeing stop is final
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+                        if (ld_sys(&H->published) <= b) st = 1;
+                        break;
+                    }
+                    if (ld_dev(&P->abort) || wall_clock64() - t0 > ticks_idle) {
+                        st = 2;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(8);
+                }
+                state = st;
+            }
+            __syncthreads();
+            if (state == 0) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");  // the host's descriptor writes
+                const PBatch &src = H->batch[slot];
+                const int n = src.n;
+                const uint64_t *w = reinterpret_cast<const uint64_t *>(src.req);
+                uint64_t *d = reinterpret_cast<uint64_t *>(T.cur.req);
+                for (int i = threadIdx.x; i < n * int(sizeof(SvReq) / 8); i += kSvWG) d[i] = w[i];
+                if (threadIdx.x == 0) {
+                    T.cur.n = n;
+                    T.cur.total_chunks = src.total_chunks;
+                    T.cur.total_items = src.total_items;
+                }
+            } else if (threadIdx.x == 0) {
+                if (state == 2) atomicOr(&P->abort, 1u);
+                __hip_atomic_store(&T.exit, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        // the other workgroups wait here for the batch (bounded by the idle limit)
+        if (!team_sync(P, T, G, ticks_idle) || ld_dev(&T.exit)) break;
+        const SvRound R{T.cur.req, T.cur.n, T.cur.total_chunks, T.cur.total_items, arena};
+        sv_count(S, R, wg, G);
+        if (!team_sync(P, T, G, ticks_step)) break;
+        for (unsigned int r = wg; r < unsigned(R.n); r += G) sv_scan_one(R, int(r));
+        if (!team_sync(P, T, G, ticks_step)) break;
+        sv_emit(S, R, wg, G);
+        if (!team_sync(P, T, G, ticks_step)) break;
+        sv_gather(S, R, wg, G);
+        if (!team_sync(P, T, G, ticks_step)) break;
+        if (wg == 0) {  // results to the host, then the completion word
+            for (int i = threadIdx.x; i < 2 * R.n; i += kSvWG) {
+                const int64_t v = reinterpret_cast<const int64_t *>(arena + R.req[i >> 1].off_meta)[i & 1];
+                __hip_atomic_store(reinterpret_cast<unsigned long long *>(&H->meta[slot][i >> 1][i & 1]),
+                                   (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");  // every wave's result stores
+            __syncthreads();
+            if (threadIdx.x == 0)
+                __hip_atomic_store(&H->done[slot], b + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+    }
+    if (wg == 0 && threadIdx.x == 0 && ld_dev(&P->abort))
+        __hip_atomic_store(&H->err, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 __global__ void k_sv_read_log_len(const Counters *C, unsigned long long *out, uint64_t cap) {
@@ -197,39 +376,6 @@ __global__ void k_sv_read_log_len(const Counters *C, unsigned long long *out, ui
 
 using Clock = std::chrono::steady_clock;
 
-// First-fit allocator of arena byte ranges (256-byte aligned) with coalescing.
-struct Arena {
-    std::map<int64_t, int64_t> free_;  // offset -> size
-    void init(int64_t bytes) { free_ = {{0, bytes}}; }
-    int64_t alloc(int64_t n) {
-        n = (n + 255) & ~int64_t(255);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= n) {
-                const int64_t off = it->first, rest = it->second - n;
-                free_.erase(it);
-                if (rest) free_[off + n] = rest;
-                return off;
-            }
-        }
-        return -1;
-    }
-    void release(int64_t off, int64_t n) {
-        n = (n + 255) & ~int64_t(255);
-        auto it = free_.emplace(off, n).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-};
 
 }  // namespace
 
@@ -248,6 +394,12 @@ struct vbh_server {
     std::vector<uint64_t> cursor;  // per client
     uint64_t end_v = 0;            // log end of the published version
     uint32_t version = 0;
+    // persistent form
+    PHost *H = nullptr;             // pinned, coherent ring shared with the launch (host address)
+    PHost *dH = nullptr;            // the same memory as the device addresses it
+    PDev *P = nullptr;              // device-side barrier and abort state
+    unsigned pgrid = 0;             // workgroups of the launch
+    long long ticks_per_s = 100000000;  // constant wall clock of the device
 };
 
 namespace {
@@ -281,6 +433,193 @@ int read_log_end(vbh_server *v, hipStream_t st, uint64_t *out) {
     return VBH_OK;
 }
 
+// The persistent form of vbh_server_run.  One launch serves the batches of one scene
+// version: when a frame is due, the launch is stopped (it finishes the published batches),
+// the frame is fused with its MC update, and a new launch serves the next version.  The
+// launch is also stopped while no work is pending, and restarted when some arrives.
+int run_persistent(vbh_server *v, const vbh_request *reqs, int64_t n_req, const vbh_frame_feed *frames,
+                   int64_t n_frames, vbh_request_result *res, Clock::time_point t0) {
+    vbh_scene *sc = v->scene;
+    PHost *H = v->H;
+    hipStream_t st = v->streams[0];
+    const int teams = std::min(v->cfg.n_streams, kMaxTeams);
+    const long long ticks_idle = 10 * v->ticks_per_s, ticks_step = 5 * v->ticks_per_s;
+    const int64_t cap_chunks_per_req = (sc->p.log_capacity + kSvChunk - 1) / kSvChunk + 1;
+    struct Batch {
+        unsigned long long seq;
+        std::vector<InFlight> items;
+    };
+    std::vector<std::deque<int64_t>> queue(size_t(v->cfg.n_clients));
+    std::vector<char> busy(size_t(v->cfg.n_clients), 0);
+    std::vector<int> free_slots;
+    for (int i = v->cfg.max_inflight - 1; i >= 0; --i) free_slots.push_back(i);
+    std::deque<Batch> inflight;
+    bool running = false;
+    unsigned long long published = 0;
+    int64_t next_arrival = 0, n_done = 0, fi = 0;
+    int rc = VBH_OK;
+
+    auto finish = [&](Batch &bt, int slot, double tdone) {
+        for (size_t i = 0; i < bt.items.size(); ++i) {
+            const InFlight &f = bt.items[i];
+            vbh_request_result &r = res[f.req];
+            r.count = H->meta[slot][i][0];
+            r.cursor_out = uint64_t(H->meta[slot][i][1]);
+            r.done_s = tdone;
+            r.status = VBH_OK;
+            const int c = reqs[f.req].client;
+            v->cursor[size_t(c)] = r.cursor_out;
+            busy[size_t(c)] = 0;
+            v->alloc.release(f.off, f.bytes);
+            free_slots.push_back(f.slot);
+            ++n_done;
+        }
+    };
+    auto poll = [&]() {
+        const double tdone = secs(t0);
+        for (auto it = inflight.begin(); it != inflight.end();) {
+            const int slot = int(it->seq % kPRing);
+            if (__atomic_load_n(&H->done[slot], __ATOMIC_ACQUIRE) == it->seq + 1) {
+                finish(*it, slot, tdone);
+                it = inflight.erase(it);
+            } else {
+                ++it;
+            }
+        }
+    };
+    auto launch = [&]() -> int {
+        H->published = 0;
+        H->stop = 0;
+        H->err = 0;
+        for (auto &d : H->done) d = 0;
+        published = 0;
+        k_sv_pinit<<<1, 64, 0, st>>>(v->P);
+        k_sv_persistent<<<v->pgrid, kSvWG, 0, st>>>(sc->d, v->dH, v->P, v->arena, teams, ticks_idle, ticks_step);
+        if (hipGetLastError() != hipSuccess) return VBH_EHIP;
+        running = true;
+        return VBH_OK;
+    };
+    auto stop = [&]() -> int {
+        if (!running) return VBH_OK;
+        __atomic_store_n(&H->stop, 1ull, __ATOMIC_RELEASE);
+        const hipError_t e = hipStreamSynchronize(st);
+        running = false;
+        poll();
+        if (e != hipSuccess || __atomic_load_n(&H->err, __ATOMIC_ACQUIRE) || !inflight.empty()) return VBH_EHIP;
+        return VBH_OK;
+    };
+    auto fuse = [&](const vbh_frame_feed &fr) -> int {
+        if (!fr.d_depth || fr.frame_id <= sc->last_frame) return VBH_EINVAL;
+        int r = scene_fuse(sc, fr.d_depth, fr.d_rgb, fr.pose_c2w, fr.frame_id, true, v->istream);
+        uint64_t end = 0;
+        if (r == VBH_OK) r = read_log_end(v, v->istream, &end);
+        if (r == VBH_OK) {
+            v->end_v = end;
+            v->version = fr.frame_id;
+        }
+        return r;
+    };
+
+    while (n_done < n_req && rc == VBH_OK) {
+        const double now = secs(t0);
+        while (next_arrival < n_req && reqs[next_arrival].arrival_s <= now) {
+            queue[size_t(reqs[next_arrival].client)].push_back(next_arrival);
+            ++next_arrival;
+        }
+        if (fi < n_frames && frames[fi].time_s <= now) {  // a new scene version
+            rc = stop();
+            if (rc == VBH_OK) rc = fuse(frames[fi]);
+            ++fi;
+            continue;
+        }
+        // admit one batch into a free ring slot (a stopped launch is restarted first, since a
+        // new launch numbers its batches from 0)
+        if (!running) {
+            bool work = false;
+            for (int c = 0; c < v->cfg.n_clients && !work; ++c) work = !busy[size_t(c)] && !queue[size_t(c)].empty();
+            if (work) rc = launch();
+            if (rc != VBH_OK) break;
+        }
+        const int slot = int(published % kPRing);
+        bool slot_free = running && inflight.size() < size_t(kPRing);
+        for (const Batch &bt : inflight) slot_free = slot_free && int(bt.seq % kPRing) != slot;
+        if (slot_free) {
+            PBatch &B = H->batch[slot];
+            Batch bt;
+            bt.seq = published;
+            int64_t chunks = 0, items = 0;
+            for (int c = 0; c < v->cfg.n_clients && int(bt.items.size()) < v->cfg.max_batch; ++c) {
+                if (busy[size_t(c)] || queue[size_t(c)].empty() || free_slots.empty()) continue;
+                const int64_t ri = queue[size_t(c)].front();
+                const uint64_t cur = v->cursor[size_t(c)];
+                const int64_t lim = reqs[ri].limit;
+                const int64_t nch = cur < v->end_v ? int64_t((v->end_v - cur + kSvChunk - 1) / kSvChunk) : 0;
+                const int64_t bytes = req_bytes(lim, nch);
+                if (nch > cap_chunks_per_req || bytes > v->cfg.arena_bytes) {
+                    res[ri].status = VBH_EINVAL;  // can never fit
+                    queue[size_t(c)].pop_front();
+                    ++n_done;
+                    continue;
+                }
+                const int64_t off = v->alloc.alloc(bytes);
+                if (off < 0) continue;  // admitted later, when memory frees up
+                queue[size_t(c)].pop_front();
+                busy[size_t(c)] = 1;
+                const int rs = free_slots.back();
+                free_slots.pop_back();
+                SvReq &q = B.req[bt.items.size()];
+                auto al = [](int64_t n) { return (n + 255) & ~int64_t(255); };
+                q.cursor = cur;
+                q.end = v->end_v;
+                q.limit = lim;
+                q.chunk_base = chunks;
+                q.n_chunks = nch;
+                q.item_base = items;
+                q.off_sel = off;
+                q.off_cnt = q.off_sel + al(lim * 4);
+                q.off_keys = q.off_cnt + al(nch * 8);
+                q.off_mc = q.off_keys + al(lim * 12);
+                q.off_meta = q.off_mc + al(lim * 2048);
+                q.keys_out = reqs[ri].d_keys_out;
+                q.mc_out = reinterpret_cast<uint32_t *>(reqs[ri].d_mc_out);
+                chunks += nch;
+                items += lim;
+                res[ri].arrival_s = reqs[ri].arrival_s;
+                res[ri].admit_s = now;
+                res[ri].cursor_in = cur;
+                res[ri].version = v->version;
+                bt.items.push_back({ri, off, bytes, rs});
+            }
+            if (!bt.items.empty()) {
+                B.n = int32_t(bt.items.size());
+                B.total_chunks = chunks;
+                B.total_items = items;
+                __atomic_store_n(&H->published, published + 1, __ATOMIC_RELEASE);
+                ++published;
+                inflight.push_back(std::move(bt));
+            }
+        }
+        poll();
+        if (running && !inflight.empty() && hipStreamQuery(st) != hipErrorNotReady) rc = VBH_EHIP;  // the launch left
+        // idle: nothing in flight or queued and the next event is not imminent
+        if (running && inflight.empty()) {
+            bool queued = false;
+            for (const auto &q : queue) queued = queued || !q.empty();
+            const double next = std::min(next_arrival < n_req ? reqs[next_arrival].arrival_s : 1e300,
+                                         fi < n_frames ? frames[fi].time_s : 1e300);
+            if (!queued && next - now > 0.5) rc = stop();
+        }
+        std::this_thread::yield();
+    }
+    const int rs = stop();
+    if (rc == VBH_OK) rc = rs;
+    for (; rc == VBH_OK && fi < n_frames; ++fi) {  // the rest of the frame schedule
+        while (secs(t0) < frames[fi].time_s) std::this_thread::sleep_for(std::chrono::microseconds(50));
+        rc = fuse(frames[fi]);
+    }
+    return rc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -288,7 +627,9 @@ extern "C" {
 int vbh_server_create(vbh_scene *scene, const vbh_server_config *cfg, vbh_server **out) {
     if (!out || !scene || !cfg || cfg->arena_bytes < 4096 || cfg->max_inflight < 1 || cfg->max_inflight > 4096 ||
         cfg->n_streams < 1 || cfg->n_streams > 8 || cfg->n_clients < 1 || cfg->max_batch < 1 ||
-        cfg->max_batch > kMaxBatch || int64_t(cfg->max_inflight) * cfg->max_batch > (int64_t(1) << 18))
+        cfg->max_batch > kMaxBatch || int64_t(cfg->max_inflight) * cfg->max_batch > (int64_t(1) << 18) ||
+        (cfg->mode != VBH_SERVE_ROUNDS && cfg->mode != VBH_SERVE_PERSISTENT) || cfg->workgroups < 0 ||
+        cfg->workgroups > 4096 || (cfg->mode == VBH_SERVE_PERSISTENT && cfg->n_streams > kMaxTeams))
         return VBH_EINVAL;
     *out = nullptr;
     vbh_server *v = new (std::nothrow) vbh_server();
@@ -307,6 +648,20 @@ int vbh_server_create(vbh_scene *scene, const vbh_server_config *cfg, vbh_server
         if (ok) v->streams.push_back(s);
     }
     ok = ok && hipStreamCreateWithFlags(&v->istream, hipStreamNonBlocking) == hipSuccess;
+    if (ok && cfg->mode == VBH_SERVE_PERSISTENT) {
+        int dev = 0, khz = 0;
+        ok = hipHostMalloc(reinterpret_cast<void **>(&v->H), sizeof(PHost), hipHostMallocCoherent | hipHostMallocMapped) ==
+                 hipSuccess &&
+             hipHostGetDevicePointer(reinterpret_cast<void **>(&v->dH), v->H, 0) == hipSuccess &&
+             hipMalloc(&v->P, sizeof(PDev)) == hipSuccess && hipGetDevice(&dev) == hipSuccess &&
+             hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess;
+        if (ok) {
+            std::memset(v->H, 0, sizeof(PHost));
+            v->ticks_per_s = khz > 0 ? (long long)khz * 1000 : v->ticks_per_s;
+            const int64_t want = cfg->workgroups > 0 ? cfg->workgroups : int64_t(scene->cus) * 2;
+            v->pgrid = unsigned(std::max<int64_t>(want, std::min(cfg->n_streams, kMaxTeams)));
+        }
+    }
     if (!ok) {
         vbh_server_destroy(v);
         return VBH_ENOMEM;
@@ -337,6 +692,8 @@ void vbh_server_destroy(vbh_server *v) {
     if (v->h_meta) (void)hipHostFree(v->h_meta);
     if (v->d_len) (void)hipFree(v->d_len);
     if (v->h_len) (void)hipHostFree(v->h_len);
+    if (v->H) (void)hipHostFree(v->H);
+    if (v->P) (void)hipFree(v->P);
     delete v;
 }
 
@@ -369,6 +726,7 @@ int vbh_server_run(vbh_server *v, const vbh_request *reqs, int64_t n_req, const 
     if (read_log_end(v, v->istream, &v->end_v) != VBH_OK) return VBH_EHIP;
     v->version = sc->last_frame;
     const auto t0 = Clock::now();
+    if (v->cfg.mode == VBH_SERVE_PERSISTENT) return run_persistent(v, reqs, n_req, frames, n_frames, res, t0);
     // --- gate between serving and the MC update of fused frames
     std::mutex mu;
     std::condition_variable cv;

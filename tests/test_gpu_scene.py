@@ -351,3 +351,32 @@ def test_full_size_long_run(orc):
     say(f"  max W {W.max()}")
     assert W.max() >= 100
     mc_on_identical_input(orc, configs.FULL_VOL, configs.FULL_CAM, keys, F, W, rgb_, gmc, grgb)
+
+
+def test_integrate_blocks_against_oracle(orc):
+    """Integration of a frame into an explicit block list (the band blocks of that frame,
+    a slab of blocks across the room that are mostly new and partly in free space, and
+    duplicates), then a band-fused frame on top: touched, new and MC sets, state and MC
+    voxels against the oracle."""
+    vbh = require_gpu()
+    _, depth, rgb, poses = configs.tiny_inputs(8)
+    G, O = make_pair(vbh, orc, configs.TINY_VOL, configs.TINY_CAM)
+    integrate_both(G, O, depth, rgb, poses, range(3))
+    scratch = orc.Scene(configs.TINY_VOL, configs.TINY_CAM)
+    assert scratch.integrate(depth[3].numpy(), rgb[3].numpy(), poses[3], 1) == 0
+    band = scratch.last_touched()
+    slab = np.array([(x, y, z) for x in range(-13, 13) for y in range(-13, 13) for z in range(-2, 2)], np.int32)
+    rng = np.random.default_rng(11)
+    lst = np.concatenate([band, slab, band[rng.integers(0, band.shape[0], 200)]])
+    lst = lst[rng.permutation(lst.shape[0])]
+    G.vbh_integrate_blocks(to_dev(lst), to_dev(depth[3].numpy()), to_dev(rgb[3].numpy()), poses[3], 4)
+    assert O.integrate_blocks(lst, depth[3].numpy(), rgb[3].numpy(), poses[3], 4) == 0
+    st = G.vbh_scene_stats()
+    say(f"  listed {lst.shape[0]} keys: touched {st['n_touched']} new {st['n_new']} mc {st['n_mc']}")
+    assert keyset(G.vbh_scene_last_touched()) == keyset(O.last_touched())
+    assert st["n_touched"] == O.last_touched().shape[0] and st["n_new"] == O.last_new().shape[0]
+    assert keyset(G.vbh_scene_last_mc()) == keyset(O.last_mc_updated())
+    assert G.vbh_scene_status() == 0
+    integrate_both(G, O, depth, rgb, poses, [4], first_id=5)
+    keys, F, W, rgb_, gmc, grgb = compare_state(G, O)
+    mc_on_identical_input(orc, configs.TINY_VOL, configs.TINY_CAM, keys, F, W, rgb_, gmc, grgb)

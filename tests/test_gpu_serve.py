@@ -80,11 +80,15 @@ def log_uniform(rng, n, lo, hi):
     return np.floor(10 ** rng.uniform(np.log10(lo), np.log10(hi), n)).astype(np.int64)
 
 
-def test_alone_equals_mix_static_scene():
+MODES = [0, 1]  # rounds of kernels on streams; one persistent launch per scene version
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_alone_equals_mix_static_scene(mode):
     vbh = require_gpu()
     S, O, _, _, _ = tiny_scene(vbh, 32, with_oracle=True)
     nb = S.vbh_scene_stats()["n_blocks"]
-    srv = vbh.Server(S, arena_bytes=256 << 20, max_inflight=32, n_streams=4, n_clients=8, max_batch=12)
+    srv = vbh.Server(S, arena_bytes=256 << 20, max_inflight=32, n_streams=4, n_clients=8, max_batch=12, mode=mode)
     rng = np.random.default_rng(0)
     n = 64
     clients = np.arange(n) % 8
@@ -93,7 +97,7 @@ def test_alone_equals_mix_static_scene():
     outs = out_buffers(limits)
     res = srv.vbh_server_run(clients, limits, arrivals, outs)
     assert (res["status"] == 0).all()
-    say(f"[serve static] {nb} blocks, {n} requests, {res['count'].sum()} blocks served")
+    say(f"[serve static mode={mode}] {nb} blocks, {n} requests, {res['count'].sum()} blocks served")
     blocks, near = oracle_replay(O, 8, clients, limits, res, outs)
     say(f"[serve static] oracle replay: {blocks} blocks, {near} MC voxels at |F| <= 1e-5")
     assert blocks == res["count"].sum()
@@ -151,11 +155,12 @@ def expected_pages(fr, keys, cursor, limit, version):
     return sel, nxt_cursor, nxt
 
 
-def test_concurrent_integration_versions():
+@pytest.mark.parametrize("mode", MODES)
+def test_concurrent_integration_versions(mode):
     vbh = require_gpu()
     S, O, hdepth, hrgb, poses = tiny_scene(vbh, 8, with_oracle=True)
     depth, rgb = hdepth.cuda(), hrgb.cuda()
-    srv = vbh.Server(S, arena_bytes=512 << 20, max_inflight=64, n_streams=4, n_clients=8, max_batch=16)
+    srv = vbh.Server(S, arena_bytes=512 << 20, max_inflight=64, n_streams=4, n_clients=8, max_batch=16, mode=mode)
     frames = [(depth[f].contiguous(), rgb[f].contiguous(), poses[f], 0.004 * (f - 7), f + 1) for f in range(8, 32)]
     rng = np.random.default_rng(1)
     n = 160
@@ -206,7 +211,8 @@ def test_concurrent_integration_versions():
     assert blocks == res["count"].sum()
 
 
-def test_large_written_scene_against_oracle():
+@pytest.mark.parametrize("mode", MODES)
+def test_large_written_scene_against_oracle(mode):
     """150k blocks of the serving scene written analytically (two updates), 8 clients,
     48 requests with sizes log-uniform in [10^2, 10^5] arriving together: every answer and
     its MC voxels against the oracle's stream sets, bit-exact."""
@@ -235,7 +241,7 @@ def test_large_written_scene_against_oracle():
     limits[3] = 100_000
     arrivals = np.zeros(n)
     outs = out_buffers(limits)
-    srv = vbh.Server(S, arena_bytes=1 << 30, max_inflight=32, n_streams=4, n_clients=8, max_batch=16)
+    srv = vbh.Server(S, arena_bytes=1 << 30, max_inflight=32, n_streams=4, n_clients=8, max_batch=16, mode=mode)
     res = srv.vbh_server_run(clients, limits, arrivals, outs)
     assert (res["status"] == 0).all()
     say(f"[serve large] {n} requests, {res['count'].sum()} blocks served, "
@@ -245,11 +251,13 @@ def test_large_written_scene_against_oracle():
     assert blocks == res["count"].sum()
 
 
-def test_admission_by_memory_and_errors():
+@pytest.mark.parametrize("mode", MODES)
+def test_admission_by_memory_and_errors(mode):
     vbh = require_gpu()
     S, _, _, _ = tiny_scene(vbh, 16)
     per_req = 1000 * (4 + 12 + 2048) + 4096
-    srv = vbh.Server(S, arena_bytes=int(2.5 * per_req), max_inflight=16, n_streams=4, n_clients=8, max_batch=8)
+    srv = vbh.Server(S, arena_bytes=int(2.5 * per_req), max_inflight=16, n_streams=4, n_clients=8, max_batch=8,
+                     mode=mode)
     n = 12
     clients = np.arange(n) % 8
     limits = np.full(n, 1000)
