@@ -82,6 +82,23 @@ __device__ __forceinline__ bool entry_live(const Dev &S, uint64_t pos, uint64_t 
     return S.mc_stamp[uint32_t(e)] == uint32_t(e >> 32);
 }
 
+// Words that one workgroup writes and another reads within a launch (chunk counts and
+// prefixes, selected pool blocks, counts and cursors) are device-scope relaxed atomics:
+// coherent across the XCDs' L2s by themselves, so the persistent launch's barriers only
+// wait for their completion and need no cache write-back or invalidate.
+__device__ __forceinline__ int64_t ld_dc(const int64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dc(int64_t *p, int64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t ld_dc(const int32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dc(int32_t *p, int32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // The four steps of a round, for workgroup wg of G (a kernel's grid, or the workgroups of
 // the persistent launch).
 __device__ __forceinline__ void sv_count(const Dev &S, const SvRound &R, int64_t wg, int64_t G) {
@@ -99,7 +116,7 @@ __device__ __forceinline__ void sv_count(const Dev &S, const SvRound &R, int64_t
         if (threadIdx.x == 0) {
             int64_t s = 0;
             for (int w = 0; w < kSvWG / 64; ++w) s += part[w];
-            reinterpret_cast<int64_t *>(R.arena + q.off_cnt)[c] = s;
+            st_dc(reinterpret_cast<int64_t *>(R.arena + q.off_cnt) + c, s);
         }
         __syncthreads();
     }
@@ -114,7 +131,7 @@ __device__ __forceinline__ void sv_scan_one(const SvRound &R, int r) {
     const int64_t per = (q.n_chunks + kSvWG - 1) / kSvWG;
     const int64_t lo = threadIdx.x * per, hi = lo + per < q.n_chunks ? lo + per : q.n_chunks;
     int64_t s = 0;
-    for (int64_t c = lo; c < hi; ++c) s += cnt[c];
+    for (int64_t c = lo; c < hi; ++c) s += ld_dc(cnt + c);
     part[threadIdx.x] = s;
     __syncthreads();
     for (int o = 1; o < kSvWG; o <<= 1) {
@@ -125,16 +142,16 @@ __device__ __forceinline__ void sv_scan_one(const SvRound &R, int r) {
     }
     int64_t run = part[threadIdx.x] - s;
     for (int64_t c = lo; c < hi; ++c) {
-        const int64_t v = cnt[c];
-        cnt[c] = run;
+        const int64_t v = ld_dc(cnt + c);
+        st_dc(cnt + c, run);
         run += v;
     }
     if (threadIdx.x == kSvWG - 1) {
         const int64_t total = part[kSvWG - 1];
         int64_t *meta = reinterpret_cast<int64_t *>(R.arena + q.off_meta);
-        meta[0] = total < q.limit ? total : q.limit;
-        if (q.limit == 0) meta[1] = int64_t(q.cursor);
-        else if (total < q.limit) meta[1] = int64_t(q.end);
+        st_dc(meta, total < q.limit ? total : q.limit);
+        if (q.limit == 0) st_dc(meta + 1, int64_t(q.cursor));
+        else if (total < q.limit) st_dc(meta + 1, int64_t(q.end));
     }
 }
 
@@ -145,7 +162,7 @@ __device__ __forceinline__ void sv_emit(const Dev &S, const SvRound &R, int64_t 
         const int r = find_req(R, it, true);
         const SvReq q = R.req[r];
         const int64_t c = it - q.chunk_base;
-        int64_t rank = reinterpret_cast<const int64_t *>(R.arena + q.off_cnt)[c];
+        int64_t rank = ld_dc(reinterpret_cast<const int64_t *>(R.arena + q.off_cnt) + c);
         if (rank >= q.limit) continue;  // uniform per workgroup
         int32_t *sel = reinterpret_cast<int32_t *>(R.arena + q.off_sel);
         int64_t *meta = reinterpret_cast<int64_t *>(R.arena + q.off_meta);
@@ -162,8 +179,8 @@ __device__ __forceinline__ void sv_emit(const Dev &S, const SvRound &R, int64_t 
             }
             const int64_t rr = before + lanes_below(m);
             if (live && rr < q.limit) {
-                sel[rr] = int32_t(uint32_t(S.log[pos]));
-                if (rr == q.limit - 1) meta[1] = int64_t(pos + 1);
+                st_dc(sel + rr, int32_t(uint32_t(S.log[pos])));
+                if (rr == q.limit - 1) st_dc(meta + 1, int64_t(pos + 1));
             }
             rank += total;
             __syncthreads();
@@ -181,9 +198,9 @@ __device__ __forceinline__ void sv_gather(const Dev &S, const SvRound &R, int64_
         const int r = find_req(R, it, false);
         const SvReq q = R.req[r];
         const int64_t b = it - q.item_base;
-        const int64_t count = reinterpret_cast<const int64_t *>(R.arena + q.off_meta)[0];
+        const int64_t count = ld_dc(reinterpret_cast<const int64_t *>(R.arena + q.off_meta));
         if (b >= count) continue;
-        const int32_t pool = reinterpret_cast<const int32_t *>(R.arena + q.off_sel)[b];
+        const int32_t pool = ld_dc(reinterpret_cast<const int32_t *>(R.arena + q.off_sel) + b);
         const uint4 *src = reinterpret_cast<const uint4 *>(S.MCV + int64_t(pool) * 512);
         uint4 *dst = reinterpret_cast<uint4 *>(q.mc_out ? reinterpret_cast<char *>(q.mc_out) : R.arena + q.off_mc) +
                      b * 128;
@@ -254,19 +271,19 @@ __device__ __forceinline__ unsigned int ld_dev(const unsigned int *p) {
 }
 
 // Barrier of the team's G workgroups; false if the abort word was raised or the wait took
-// longer than `ticks` of the constant wall clock (then this workgroup raises it).
-// Every wave releases its own writes before the arrival (a workgroup barrier does not wait
-// for other waves' stores) and acquires after it.
+// longer than `ticks` of the constant wall clock (then this workgroup raises it).  Every
+// word that crosses workgroups is a device-coherent atomic, so a wave only waits for its
+// own accesses to complete before the arrival.
 __device__ bool team_sync(PDev *P, PTeam &T, unsigned int G, long long ticks) {
     __shared__ int ok;
-    __threadfence();
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
         ok = 1;
         const unsigned int g = ld_dev(&T.gen);
         if (atomicAdd(&T.count, 1u) == G - 1) {
             __hip_atomic_store(&T.count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __threadfence();
+            __builtin_amdgcn_s_waitcnt(0);
             atomicAdd(&T.gen, 1u);
         } else {
             const long long t0 = wall_clock64();
@@ -282,7 +299,6 @@ __device__ bool team_sync(PDev *P, PTeam &T, unsigned int G, long long ticks) {
         if (ld_dev(&P->abort)) ok = 0;
     }
     __syncthreads();
-    __threadfence();  // the other workgroups' writes are visible after the barrier
     return ok != 0;
 }
 
@@ -302,6 +318,7 @@ __global__ void __launch_bounds__(kSvWG) k_sv_persistent(Dev S, PHost *H, PDev *
     const unsigned int G = (gridDim.x - unsigned(team) + unsigned(teams) - 1) / unsigned(teams);
     PTeam &T = P->team[team];
     __shared__ int state;  // 0 serve, 1 stop, 2 expired
+    __shared__ SvReq s_req[kMaxBatch];
     for (unsigned long long b = unsigned(team);; b += unsigned(teams)) {
         const int slot = int(b % kPRing);
         if (wg == 0) {
@@ -329,13 +346,13 @@ __global__ void __launch_bounds__(kSvWG) k_sv_persistent(Dev S, PHost *H, PDev *
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");  // the host's descriptor writes
                 const PBatch &src = H->batch[slot];
                 const int n = src.n;
-                const uint64_t *w = reinterpret_cast<const uint64_t *>(src.req);
-                uint64_t *d = reinterpret_cast<uint64_t *>(T.cur.req);
-                for (int i = threadIdx.x; i < n * int(sizeof(SvReq) / 8); i += kSvWG) d[i] = w[i];
+                const int64_t *w = reinterpret_cast<const int64_t *>(src.req);
+                int64_t *d = reinterpret_cast<int64_t *>(T.cur.req);
+                for (int i = threadIdx.x; i < n * int(sizeof(SvReq) / 8); i += kSvWG) st_dc(d + i, w[i]);
                 if (threadIdx.x == 0) {
-                    T.cur.n = n;
-                    T.cur.total_chunks = src.total_chunks;
-                    T.cur.total_items = src.total_items;
+                    st_dc(&T.cur.total_chunks, src.total_chunks);
+                    st_dc(&T.cur.total_items, src.total_items);
+                    st_dc(&T.cur.n, int32_t(n));
                 }
             } else if (threadIdx.x == 0) {
                 if (state == 2) atomicOr(&P->abort, 1u);
@@ -344,7 +361,14 @@ __global__ void __launch_bounds__(kSvWG) k_sv_persistent(Dev S, PHost *H, PDev *
         }
         // the other workgroups wait here for the batch (bounded by the idle limit)
         if (!team_sync(P, T, G, ticks_idle) || ld_dev(&T.exit)) break;
-        const SvRound R{T.cur.req, T.cur.n, T.cur.total_chunks, T.cur.total_items, arena};
+        const int n = ld_dc(&T.cur.n);
+        {  // this workgroup's copy of the descriptors
+            const int64_t *w = reinterpret_cast<const int64_t *>(T.cur.req);
+            int64_t *d = reinterpret_cast<int64_t *>(s_req);
+            for (int i = threadIdx.x; i < n * int(sizeof(SvReq) / 8); i += kSvWG) d[i] = ld_dc(w + i);
+        }
+        __syncthreads();
+        const SvRound R{s_req, n, ld_dc(&T.cur.total_chunks), ld_dc(&T.cur.total_items), arena};
         sv_count(S, R, wg, G);
         if (!team_sync(P, T, G, ticks_step)) break;
         for (unsigned int r = wg; r < unsigned(R.n); r += G) sv_scan_one(R, int(r));
@@ -355,11 +379,11 @@ __global__ void __launch_bounds__(kSvWG) k_sv_persistent(Dev S, PHost *H, PDev *
         if (!team_sync(P, T, G, ticks_step)) break;
         if (wg == 0) {  // results to the host, then the completion word
             for (int i = threadIdx.x; i < 2 * R.n; i += kSvWG) {
-                const int64_t v = reinterpret_cast<const int64_t *>(arena + R.req[i >> 1].off_meta)[i & 1];
+                const int64_t v = ld_dc(reinterpret_cast<const int64_t *>(arena + R.req[i >> 1].off_meta) + (i & 1));
                 __hip_atomic_store(reinterpret_cast<unsigned long long *>(&H->meta[slot][i >> 1][i & 1]),
                                    (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");  // every wave's result stores
+            __builtin_amdgcn_s_waitcnt(0);  // every wave's result stores have completed
             __syncthreads();
             if (threadIdx.x == 0)
                 __hip_atomic_store(&H->done[slot], b + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
