@@ -215,6 +215,25 @@ def hash_bench(vbh, log_phases=True):
                      "mixed_mops": nm / float(np.median(mix)) / 1e3, "reps": reps}
         m.close()
         log(f"[bench] hash {name}: {out[name]}")
+    # the ceiling: uncontended random 64-bit compare-and-swaps over a 512 MiB array (larger
+    # than the 2^25-slot table and than the Infinity Cache), as many as the bulk insert makes
+    words = torch.zeros(1 << 26, dtype=torch.int64, device="cuda")
+    won = torch.zeros(1, dtype=torch.int64, device="cuda")
+    n_ops = 1 << 24
+    times = []
+    for rep in range(reps):
+        words.zero_()
+        won.zero_()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        vbh.binding.vbh_cas_ceiling(words, n_ops, 1234 + rep, won)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    out["cas_ceiling"] = {"gops": n_ops / float(np.median(times)) / 1e6, "ops": n_ops, "words": int(words.numel()),
+                          "succeeded": int(won.item()), "reps": reps,
+                          "workload": "2^24 uncontended random 64-bit atomicCAS over a 2^26-word (512 MiB) array"}
+    log(f"[bench] hash cas ceiling: {out['cas_ceiling']}")
     return out
 
 

@@ -122,6 +122,12 @@ int vbh_map_rebuild(vbh_map *m, void *stream);
 int vbh_map_clear(vbh_map *m, void *stream);
 /* Synchronising: first error recorded by kernels since the last call (then cleared). */
 int vbh_map_status(vbh_map *m, void *stream);
+/* Measurement helper: the ceiling that the map's compare-and-swaps are compared with.
+ * n_ops 64-bit compare-and-swaps (expected 0) at pseudo-random words of d_words
+ * (n_words, a power of two, caller-owned device memory, zeroed by the caller); the number
+ * that succeeded is added to *d_won (device).  Asynchronous on `stream`. */
+int vbh_cas_ceiling(unsigned long long *d_words, int64_t n_words, int64_t n_ops, uint64_t seed,
+                    unsigned long long *d_won, void *stream);
 
 /* ========================================================================= scene
  * A voxel block hashing volume (Sec. 4.1) plus the server's MC voxel block

@@ -111,6 +111,7 @@ SIGNATURES = {
     "vbh_mc_work_size": ([_I64], _I64),
     "vbh_mc_case": ([_I32, C.c_void_p], C.c_int),
     "vbh_mc_triangulate": ([_P, _P, _I64, C.c_float, _P, _P, _I64, _P, C.POINTER(_I64), _V], C.c_int),
+    "vbh_cas_ceiling": ([_P, _I64, _I64, _U64, _P, _V], C.c_int),
     "vbh_mc_triangulate_static": ([_P, _P, _I64, C.c_float, _P, _P, _I64, C.POINTER(_I64), _V], C.c_int),
     "vbh_scene_visible_blocks": ([_V, C.POINTER(C.c_float), _P, _I64, C.POINTER(_I64), _V], C.c_int),
     "vbh_server_create": ([_V, C.POINTER(vbh_server_config), C.POINTER(_V)], C.c_int),
@@ -280,6 +281,13 @@ class ChainedMap(Map):
         h = C.c_void_p()
         _check(lib().vbh_map_create_chained(buckets, excess, hash_kind, C.byref(h)), "vbh_map_create_chained")
         self.h, self.slots, self.excess = h, buckets, excess
+
+
+def vbh_cas_ceiling(words, n_ops: int, seed: int, won):
+    """n_ops 64-bit CAS (expected 0) at pseudo-random words of the int64 tensor `words`
+    (power-of-two length, zeroed); successes added to the int64 tensor `won`."""
+    _check(lib().vbh_cas_ceiling(_ptr(words, torch.int64, name="words"), words.numel(), n_ops, seed,
+                                 _ptr(won, torch.int64, 1, "won"), _stream()), "vbh_cas_ceiling")
 
 
 def vbh_mc_triangulate(keys, mcv, voxel_size: float):

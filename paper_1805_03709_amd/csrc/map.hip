@@ -120,6 +120,30 @@ __global__ void __launch_bounds__(kBlock) k_rebuild(const Slot *src, uint64_t n,
     }
 }
 
+// Thread per operation: one 64-bit compare-and-swap at a pseudo-random word of `a` (a
+// SplitMix64 step of the operation index picks it), expecting the word's initial value,
+// so with n_words >> n_ops nearly every CAS is uncontended.  The count of successes goes
+// to *won (one atomic per workgroup).
+__global__ void __launch_bounds__(kBlock) k_cas_ceiling(unsigned long long *a, uint64_t mask, int64_t n_ops,
+                                                        uint64_t seed, unsigned long long *won) {
+    __shared__ unsigned long long wg;
+    if (threadIdx.x == 0) wg = 0;
+    __syncthreads();
+    unsigned long long mine = 0;
+    for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n_ops; i += int64_t(gridDim.x) * kBlock) {
+        uint64_t z = seed + uint64_t(i) * 0x9E3779B97F4A7C15ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        const uint64_t w = z & mask;
+        mine += atomicCAS(a + w, 0ull, uint64_t(i) + 1) == 0ull;
+    }
+    mine = wave_sum(mine);
+    if (lane_id() == 0 && mine) atomicAdd(&wg, mine);
+    __syncthreads();
+    if (threadIdx.x == 0 && wg) atomicAdd(won, wg);
+}
+
 int launch_init(Slot *T, uint64_t n, hipStream_t st) {
     k_table_init<<<grid_for(int64_t(n), kBlock, 8192), kBlock, 0, st>>>(T, n);
     VBH_LAUNCHED();
@@ -299,6 +323,16 @@ int vbh_map_rebuild(vbh_map *m, void *stream) {
     }
     (void)hipFree(m->table);
     m->table = fresh;
+    return VBH_OK;
+}
+
+int vbh_cas_ceiling(unsigned long long *d_words, int64_t n_words, int64_t n_ops, uint64_t seed,
+                    unsigned long long *d_won, void *stream) {
+    if (!d_words || !d_won || n_words < 1 || (n_words & (n_words - 1)) || n_ops < 0) return VBH_EINVAL;
+    hipStream_t st = as_stream(stream);
+    k_cas_ceiling<<<grid_for(n_ops, kBlock, 1u << 16), kBlock, 0, st>>>(d_words, uint64_t(n_words - 1), n_ops, seed,
+                                                                        d_won);
+    VBH_LAUNCHED();
     return VBH_OK;
 }
 

@@ -166,3 +166,26 @@ def test_errors_are_reported():
         assert mm.vbh_map_status() == vbh.binding.VBH_EINVAL
         assert mm.vbh_find(to_dev(k)).cpu().numpy().tolist() == [ABSENT, 9]
         assert mm.vbh_map_status() == 0
+
+
+def test_cas_ceiling_helper():
+    """The measurement helper's compare-and-swaps land at the SplitMix64-chosen words: the
+    successes equal the distinct words hit, and each hit word holds one of its operations."""
+    vbh = require_gpu()
+    n_words, n_ops, seed = 1 << 12, 3000, 99
+    words = torch.zeros(n_words, dtype=torch.int64, device="cuda")
+    won = torch.zeros(1, dtype=torch.int64, device="cuda")
+    vbh.binding.vbh_cas_ceiling(words, n_ops, seed, won)
+    torch.cuda.synchronize()
+    M = (1 << 64) - 1
+    hits = {}
+    for i in range(n_ops):
+        z = (seed + i * 0x9E3779B97F4A7C15) & M
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M
+        z ^= z >> 31
+        hits.setdefault(z & (n_words - 1), set()).add(i + 1)
+    w = words.cpu().numpy()
+    assert int(won.item()) == len(hits)
+    assert set(np.flatnonzero(w).tolist()) == set(hits)
+    assert all(int(w[k]) in v for k, v in hits.items())
