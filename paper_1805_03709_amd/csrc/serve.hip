@@ -85,7 +85,8 @@ __device__ __forceinline__ bool entry_live(const Dev &S, uint64_t pos, uint64_t 
 // Words that one workgroup writes and another reads within a launch (chunk counts and
 // prefixes, selected pool blocks, counts and cursors) are device-scope relaxed atomics:
 // coherent across the XCDs' L2s by themselves, so the persistent launch's barriers only
-// wait for their completion and need no cache write-back or invalidate.
+// wait for their completion and need no invalidate.  The gather's outputs are plain
+// stores; the barrier that ends a batch writes them back (see team_sync).
 __device__ __forceinline__ int64_t ld_dc(const int64_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -272,13 +273,22 @@ __device__ __forceinline__ unsigned int ld_dev(const unsigned int *p) {
 
 // Barrier of the team's G workgroups; false if the abort word was raised or the wait took
 // longer than `ticks` of the constant wall clock (then this workgroup raises it).  Every
-// word that crosses workgroups is a device-coherent atomic, so a wave only waits for its
-// own accesses to complete before the arrival.
-__device__ bool team_sync(PDev *P, PTeam &T, unsigned int G, long long ticks) {
+// word that one workgroup writes and another reads within a batch is a device-coherent
+// atomic, so a wave only waits for its own accesses to complete before the arrival.
+// With `write_back`, the workgroup also writes its XCD's L2 back to memory before it
+// arrives: the gather's outputs are plain stores that may sit dirty in that cache, and the
+// host hands their arena range to a later batch once this one is complete.  Left dirty,
+// such a line could be evicted after the later batch has written its counts or selected
+// blocks there (device-scope stores go through to memory) and overwrite them.
+__device__ bool team_sync(PDev *P, PTeam &T, unsigned int G, long long ticks, bool write_back = false) {
     __shared__ int ok;
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
+        if (write_back) {  // every wave's stores are in L2; the write-back completes before the arrival
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __builtin_amdgcn_s_waitcnt(0);
+        }
         ok = 1;
         const unsigned int g = ld_dev(&T.gen);
         if (atomicAdd(&T.count, 1u) == G - 1) {
@@ -376,7 +386,7 @@ __global__ void __launch_bounds__(kSvWG) k_sv_persistent(Dev S, PHost *H, PDev *
         sv_emit(S, R, wg, G);
         if (!team_sync(P, T, G, ticks_step)) break;
         sv_gather(S, R, wg, G);
-        if (!team_sync(P, T, G, ticks_step)) break;
+        if (!team_sync(P, T, G, ticks_step, true)) break;
         if (wg == 0) {  // results to the host, then the completion word
             for (int i = threadIdx.x; i < 2 * R.n; i += kSvWG) {
                 const int64_t v = ld_dc(reinterpret_cast<const int64_t *>(arena + R.req[i >> 1].off_meta) + (i & 1));

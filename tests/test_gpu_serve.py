@@ -252,6 +252,42 @@ def test_large_written_scene_against_oracle(mode):
 
 
 @pytest.mark.parametrize("mode", MODES)
+def test_arena_outputs_reused(mode):
+    """Answers kept in the server's arena (no caller buffers), so later batches reuse the
+    ranges of earlier batches' MC voxel outputs (hundreds of MB through a 512 MiB arena):
+    on a written scene whose log entries are all live, request i of a client takes
+    count = min(limit, blocks left after its cursor) and moves the cursor by that much."""
+    vbh = require_gpu()
+    say(f"[serve arena reuse] mode {mode}: building analytic blocks")
+    keys, F, W, rgb = configs.analytic_blocks(configs.serve_scene(), configs.SERVE_VOL.voxel_size,
+                                              configs.SERVE_VOL.trunc, device="cuda")
+    n_blk = 150_000
+    keys, F, W, rgb = (t[:n_blk].contiguous() for t in (keys, F, W, rgb))
+    vol = configs.Volume(**{**configs.SERVE_VOL.__dict__, "slots": 1 << 19, "pool_blocks": 1 << 18,
+                            "log_capacity": 1 << 21})
+    S = vbh.Scene(vbh.make_params(vol, configs.FULL_CAM))
+    S.vbh_scene_write_blocks(keys, F, W, rgb, 1)
+    assert S.vbh_scene_status() == 0 and S.vbh_scene_stats()["log_length"] == n_blk
+    del keys, F, W, rgb
+    rng = np.random.default_rng(2064)
+    n = 80
+    clients = np.arange(n) % 8
+    limits = log_uniform(rng, n, 2000, 60_000)
+    srv = vbh.Server(S, arena_bytes=1 << 29, max_inflight=32, n_streams=4, n_clients=8, max_batch=16, mode=mode)
+    res = srv.vbh_server_run(clients, limits, np.zeros(n))
+    assert (res["status"] == 0).all()
+    cur = np.zeros(8, np.int64)
+    for i in range(n):
+        c = clients[i]
+        want = min(int(limits[i]), n_blk - int(cur[c]))
+        assert res["cursor_in"][i] == cur[c], i
+        assert res["count"][i] == want, (i, int(res["count"][i]), want)
+        cur[c] += want
+        assert res["cursor_out"][i] == cur[c], i
+    say(f"[serve arena reuse] {res['count'].sum()} blocks served")
+
+
+@pytest.mark.parametrize("mode", MODES)
 def test_admission_by_memory_and_errors(mode):
     vbh = require_gpu()
     S, _, _, _ = tiny_scene(vbh, 16)

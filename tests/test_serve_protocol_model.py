@@ -2,9 +2,10 @@
 barriers, stop and relaunch), replayed step by step under random interleavings.
 
 Each workgroup and the host are generators that yield at every access to shared memory;
-a seeded scheduler interleaves them (sequentially consistent memory: the launch orders
-its cross-workgroup accesses with release/acquire fences at every barrier and around the
-ring words).  Checked over many seeds and shapes (teams, workgroups per team, batches):
+a seeded scheduler interleaves them (sequentially consistent memory: within a batch the
+launch's cross-workgroup words are device-coherent atomics, each wave's accesses complete
+before it arrives at a barrier, and the ring words are system-scope atomics with fences;
+the arena's reuse under write-back caches is modelled in test_serve_cache_model).  Checked over many seeds and shapes (teams, workgroups per team, batches):
 - every published batch is served exactly once, with the descriptors the host wrote;
 - within a batch, no workgroup starts a step before every workgroup of its team finished
   the previous one;
