@@ -195,6 +195,15 @@ int vbh_integrate_frame(vbh_scene *s, const float *d_depth, const uint8_t *d_rgb
 int vbh_integrate_blocks(vbh_scene *s, const int32_t *d_keys, int64_t n, const float *d_depth, const uint8_t *d_rgb,
                          const float *pose_c2w, uint32_t frame_id, void *stream);
 
+/* Self-check of the division that step 2 uses to project a voxel (its pixel is
+ * floor(fx * x/z + cx + 1/2), floor(fy * y/z + cy + 1/2)): for each of n seeded operand pairs
+ * (divisor in [2^-32, 2^32), with an all-ones significand if all_ones = 1, else a random one;
+ * dividend of either sign in [2^-90, 2^32)), the kernel's reciprocal-based quotient is
+ * compared bit for bit with the correctly rounded quotient; the number of pairs that differ
+ * is written to *d_bad (device, caller-owned).  Asynchronous on `stream`; n < 0, a NULL
+ * d_bad or another all_ones value give VBH_EINVAL. */
+int vbh_check_division(int64_t n, uint64_t seed, int32_t all_ones, unsigned long long *d_bad, void *stream);
+
 /* Fuse n consecutive frames, each exactly as vbh_integrate_frame would, in order: d_depth
  * float32 [n][H*W], d_rgb uint8 [n][H*W*3] or NULL, poses_c2w a HOST array of n*12 floats
  * (copied), frame ids first_frame_id .. first_frame_id + n - 1 (first_frame_id > 0 and

@@ -112,6 +112,7 @@ SIGNATURES = {
     "vbh_mc_case": ([_I32, C.c_void_p], C.c_int),
     "vbh_mc_triangulate": ([_P, _P, _I64, C.c_float, _P, _P, _I64, _P, C.POINTER(_I64), _V], C.c_int),
     "vbh_cas_ceiling": ([_P, _I64, _I64, _U64, _P, _V], C.c_int),
+    "vbh_check_division": ([_I64, _U64, C.c_int32, _P, _V], C.c_int),
     "vbh_mc_triangulate_static": ([_P, _P, _I64, C.c_float, _P, _P, _I64, C.POINTER(_I64), _V], C.c_int),
     "vbh_scene_visible_blocks": ([_V, C.POINTER(C.c_float), _P, _I64, C.POINTER(_I64), _V], C.c_int),
     "vbh_server_create": ([_V, C.POINTER(vbh_server_config), C.POINTER(_V)], C.c_int),
@@ -288,6 +289,13 @@ def vbh_cas_ceiling(words, n_ops: int, seed: int, won):
     (power-of-two length, zeroed); successes added to the int64 tensor `won`."""
     _check(lib().vbh_cas_ceiling(_ptr(words, torch.int64, name="words"), words.numel(), n_ops, seed,
                                  _ptr(won, torch.int64, 1, "won"), _stream()), "vbh_cas_ceiling")
+
+
+def vbh_check_division(n: int, seed: int, all_ones: int, bad):
+    """Count (into the int64 tensor `bad`) the n seeded operand pairs whose reciprocal-based
+    projection quotient differs from the correctly rounded one."""
+    _check(lib().vbh_check_division(n, seed, all_ones, _ptr(bad, torch.int64, 1, "bad"), _stream()),
+           "vbh_check_division")
 
 
 def vbh_mc_triangulate(keys, mcv, voxel_size: float):

@@ -8,12 +8,14 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <array>
 #include <cmath>
 #include <cstring>
 #include <new>
 #include <vector>
 
+#include "fastdiv.hpp"
 #include "scene.hpp"
 
 using namespace vbh;
@@ -421,8 +423,17 @@ __global__ void __launch_bounds__(kBlock) k_integrate(Dev S, Frame fr, int with_
             pz[j] = pcz;
             pix[j] = -1;
             if (pool >= 0 && pcz > 0.0f) {
-                const float fu = floorf((fr.fx * (pcx / pcz) + fr.cx) + 0.5f);
-                const float fv = floorf((fr.fy * (pcy / pcz) + fr.cy) + 0.5f);
+                float qx, qy;
+                if (fr.fast_div && pcz >= 0x1p-32f) {  // one reciprocal for both quotients
+                    const float y = refine_rcp(pcz, __builtin_amdgcn_rcpf(pcz));
+                    qx = corrected_quotient(pcx, pcz, y);
+                    qy = corrected_quotient(pcy, pcz, y);
+                } else {
+                    qx = pcx / pcz;
+                    qy = pcy / pcz;
+                }
+                const float fu = floorf((fr.fx * qx + fr.cx) + 0.5f);
+                const float fv = floorf((fr.fy * qy + fr.cy) + 0.5f);
                 if (fu >= 0.0f && fu < float(fr.W) && fv >= 0.0f && fv < float(fr.H))
                     pix[j] = int32_t(__umul24(uint32_t(fv), uint32_t(fr.W)) + uint32_t(fu));
             }
@@ -1168,6 +1179,18 @@ Frame make_frame(const vbh_scene *s, const float *pose) {
     f.vs = s->p.voxel_size;
     f.mu = s->p.trunc;
     f.m_band = s->m_band;
+    // The integration kernel's reciprocal-based quotients pc_x / pc_z and pc_y / pc_z equal
+    // the correctly rounded ones for |pc| <= 2^32 and pc_z >= 2^-32 (the kernel checks the
+    // latter); a quotient below 2^-56 yields the same pixel as the exact one if |fx|, |fy|
+    // <= 2^20.  A voxel's camera coordinate is at most the largest column sum of |R| times
+    // the largest |voxel centre - t|, with block coordinates below 2^20 in magnitude.
+    double col = 0.0, tmax = 0.0;
+    for (int j = 0; j < 3; ++j) {
+        col = std::max(col, std::fabs(double(pose[j])) + std::fabs(double(pose[4 + j])) + std::fabs(double(pose[8 + j])));
+        tmax = std::max(tmax, std::fabs(double(pose[4 * j + 3])));
+    }
+    const double bound = 1.001 * col * ((double(1 << 23) + 8.0) * double(f.vs) + tmax);
+    f.fast_div = int(bound <= 0x1p32 && std::fabs(double(f.fx)) <= 0x1p20 && std::fabs(double(f.fy)) <= 0x1p20);
     return f;
 }
 }  // namespace vbh

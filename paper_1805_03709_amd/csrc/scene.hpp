@@ -88,6 +88,7 @@ struct Frame {
     float dmin, dmax;
     float vs, mu;
     int m_band;
+    int fast_div;  // 1: coordinates and focal lengths admit the reciprocal-based quotient
 };
 
 // The touched list and MC list of update `seq`: double-buffered, so that the allocation
