@@ -115,23 +115,24 @@ __device__ __forceinline__ void flush_mc(int32_t *mclist, FrameCounters *fc, Sta
 // the same sample of the left or upper pixel of its 8x8 wave tile is dropped at once, and
 // the rest go into an LDS hash set.  Only the tile's distinct keys then reach the global
 // table, one thread each: its home slot's key and frame stamp are read together, absent
-// keys are claimed with a CAS (and get pool blocks from one reservation per workgroup),
-// and the thread that raises a block's frame stamp appends it to the touched list (one
-// atomic per workgroup, shared with the new-block count).
+// keys are claimed with a CAS (and get pool blocks from one reservation per wave, issued
+// together with the frame-stamp raise), and the thread that raises a block's frame stamp
+// appends it to the touched list (one atomic per workgroup and round, shared with the
+// MC-list space).
 //
 // With `mark`, the kernel also forms the update's MC set.  Blocks that existed before the
 // frame are found by any probe (keys never move); a block allocated by this frame is
 // touched, so it enters the set as a touched block whether or not a neighbour's probe
 // saw it.  Hence: the appending thread of a touched block B marks B's existing negative
-// neighbours and, if B's pool block is already known, B itself; the claiming thread of a
-// new block marks it once its pool block is assigned.
+// neighbours and, if B's pool block is already known, B itself; the workgroup that claims
+// a new block marks it in the same marking step.
 //
 constexpr int kAllocThreads = 512;  // 32x16 pixels: eight 8x8 wave tiles
 constexpr int kSetSlots = 2048;     // LDS hash set of keys (load <= 1/2, see kListFlush)
 constexpr int kListCap = 1024;      // distinct keys collected before they are processed
 constexpr int kListFlush = kListCap - kAllocThreads;  // one sample step adds <= 512 keys
-constexpr int kMcCap = 2048;        // staged MC-set blocks (<= 1024 from claims, then
-                                    // flushed above kMcCap - 512 after each marking round)
+constexpr int kMcCap = 2048;        // staged MC-set blocks (flushed above kMcCap - 512
+                                    // after each marking round of <= 512 items)
 
 // Workgroup-shared state of the allocation.
 struct AllocShared {
@@ -140,8 +141,9 @@ struct AllocShared {
     int32_t appended[kListCap];
     uint16_t app_idx[kListCap];  // list index of each appended block
     int32_t app_pool[kListCap];  // its pool block if it still has to be marked, else -1
+    int32_t self_pool[kListCap]; // pool blocks this workgroup claimed (marked by it)
     StageBuf<kMcCap> mcb;
-    unsigned int n_list, n_app, n_claim, n_new_wg;
+    unsigned int n_list, n_app, n_self, n_new_wg;
     unsigned long long pool_base;
 };
 
@@ -160,7 +162,8 @@ __device__ __forceinline__ void alloc_tile(const Dev &S, const Frame &fr, const 
     uint16_t *app_idx = sh.app_idx;
     int32_t *app_pool = sh.app_pool;
     StageBuf<kMcCap> &mcb = sh.mcb;
-    unsigned int &n_list = sh.n_list, &n_app = sh.n_app, &n_claim = sh.n_claim, &n_new_wg = sh.n_new_wg;
+    int32_t *self_pool = sh.self_pool;
+    unsigned int &n_list = sh.n_list, &n_app = sh.n_app, &n_self = sh.n_self, &n_new_wg = sh.n_new_wg;
     unsigned long long &pool_base = sh.pool_base;
     FrameCounters *fc = &S.C->fc[seq & (kRing - 1)];
     if (tx == 0 && ty == 0 && threadIdx.x == 0) begin_update(S, seq);
@@ -168,7 +171,7 @@ __device__ __forceinline__ void alloc_tile(const Dev &S, const Frame &fr, const 
     if (threadIdx.x == 0) {
         n_list = 0;
         n_app = 0;
-        n_claim = 0;
+        n_self = 0;
         n_new_wg = 0;
         mcb.count = 0;
     }
@@ -250,7 +253,6 @@ __device__ __forceinline__ void alloc_tile(const Dev &S, const Frame &fr, const 
             int32_t slot = -1, pool = -1;  // pool: the block's pool index if known, else -1
             bool claimed = false, stamp_now = false;
             uint64_t key = kEmpty;
-            unsigned int cidx = 0;
             if (i < nl) {
                 key = list[i];
                 int32_t x, y, z;
@@ -272,20 +274,20 @@ __device__ __forceinline__ void alloc_tile(const Dev &S, const Frame &fr, const 
                         pool = v >= 0 ? v : -1;
                     }
                 }
-                if (claimed) cidx = atomicAdd(&n_claim, 1u);
             }
-            __syncthreads();
-            const unsigned int nc = n_claim;
-            __syncthreads();  // every thread has read n_claim before it is reset
-            if (nc) {  // uniform: one pool reservation per workgroup and round
-                if (threadIdx.x == 0) {
-                    pool_base = atomicAdd(&S.C->pool_next, (unsigned long long)nc);
-                    n_new_wg += nc;
-                    n_claim = 0;
-                }
-                __syncthreads();
+            // A claimed key's pool block (one reservation per wave that claims) and every
+            // found key's frame stamp are requested together: neither waits for the other.
+            const unsigned long long cm = __ballot(claimed);
+            unsigned long long pb = 0;
+            if (cm && lane == __builtin_ctzll(cm)) {
+                pb = atomicAdd(&S.C->pool_next, (unsigned long long)__popcll(cm));
+                atomicAdd(&n_new_wg, unsigned(__popcll(cm)));  // LDS
+            }
+            const bool raise = slot >= 0 && !stamp_now;
+            const uint32_t old_stamp = raise ? atomicMax(&S.T[slot].stamp, frame) : frame;
+            if (cm) {
+                pb = __shfl(pb, __builtin_ctzll(cm)) + (unsigned long long)lanes_below(cm);
                 if (claimed) {
-                    const unsigned long long pb = pool_base + cidx;
                     if (int64_t(pb) < S.pool_cap) {
                         S.pool_key[pb] = key;
                         st_val(S.T + slot, int32_t(pb));
@@ -295,9 +297,18 @@ __device__ __forceinline__ void alloc_tile(const Dev &S, const Frame &fr, const 
                         raise_err(&S.C->err, kErrPoolFull);
                     }
                 }
-                if (mark) stage_put(mcb, claimed && try_mark(S, pool, frame), pool);  // new block: its claimer marks it
+                // a new block is marked by its claimer (in the marking step below)
+                const bool self = mark && claimed && pool >= 0;
+                const unsigned long long sm = __ballot(self);
+                if (sm) {
+                    const int leader = __builtin_ctzll(sm);
+                    unsigned int p0 = 0;
+                    if (lane == leader) p0 = atomicAdd(&n_self, unsigned(__popcll(sm)));
+                    p0 = __shfl(p0, leader);
+                    if (self) self_pool[p0 + unsigned(lanes_below(sm))] = pool;
+                }
             }
-            const bool app = slot >= 0 && !stamp_now && atomicMax(&S.T[slot].stamp, frame) < frame;
+            const bool app = raise && old_stamp < frame;
             const unsigned long long m = __ballot(app);
             if (m) {
                 const int leader = __builtin_ctzll(m);
@@ -313,22 +324,13 @@ __device__ __forceinline__ void alloc_tile(const Dev &S, const Frame &fr, const 
             }
         }
         __syncthreads();
-        // touched-list space and the new-block count in one 64-bit atomic
-        if (threadIdx.x == 0) {
-            const unsigned long long add = (unsigned long long)n_new_wg << 32 | n_app;
-            const unsigned long long old =
-                add ? atomicAdd(reinterpret_cast<unsigned long long *>(&fc->n_touched), add) : 0ull;
-            pool_base = old & 0xFFFFFFFFull;  // reused as the list base
-            n_new_wg = 0;
-        }
-        __syncthreads();
-        for (unsigned int i = threadIdx.x; i < n_app; i += kAllocThreads) touched_of(S, seq)[pool_base + i] = appended[i];
-        if (mark) {  // uniform: MC-set marking, thread per (appended block, e in {0,1}^3)
-            const unsigned int items = n_app * 8u;
+        if (mark) {  // uniform: MC-set marking, thread per (appended block, e in {0,1}^3) and
+                     // per block this workgroup claimed
+            const unsigned int n8 = n_app * 8u, items = n8 + n_self;
             for (unsigned int r = 0; r < items; r += kAllocThreads) {
                 const unsigned int it = r + threadIdx.x;
                 int32_t target = -1;
-                if (it < items) {
+                if (it < n8) {
                     const unsigned int b = it >> 3, e = it & 7u;
                     if (e == 0) {
                         target = app_pool[b];
@@ -337,6 +339,8 @@ __device__ __forceinline__ void alloc_tile(const Dev &S, const Frame &fr, const 
                         unpack_key(list[app_idx[b]], x, y, z);
                         target = negative_neighbour(S, x, y, z, int(e));
                     }
+                } else if (it < items) {
+                    target = self_pool[it - n8];
                 }
                 stage_put(mcb, try_mark(S, target, frame), target);
                 __syncthreads();
@@ -345,7 +349,24 @@ __device__ __forceinline__ void alloc_tile(const Dev &S, const Frame &fr, const 
                 if (c > unsigned(kMcCap - kAllocThreads)) flush_mc(mclist_of(S, seq), fc, mcb);
             }
             __syncthreads();
-            if (mcb.count) flush_mc(mclist_of(S, seq), fc, mcb);  // no thread stages again before this flush
+        }
+        // touched-list space and the rest of the MC-list space in one 64-bit atomic (the two
+        // counts share a word); the new-block count needs no reply
+        if (threadIdx.x == 0) {
+            const unsigned int nm = mark ? mcb.count : 0u;
+            const unsigned long long add = (unsigned long long)nm << 32 | n_app;
+            const unsigned long long old =
+                add ? atomicAdd(reinterpret_cast<unsigned long long *>(&fc->n_touched), add) : 0ull;
+            pool_base = old & 0xFFFFFFFFull;  // reused as the touched-list base
+            mcb.base = old >> 32;
+            if (n_new_wg) atomicAdd(&fc->n_new, n_new_wg);
+            n_new_wg = 0;
+        }
+        __syncthreads();
+        for (unsigned int i = threadIdx.x; i < n_app; i += kAllocThreads) touched_of(S, seq)[pool_base + i] = appended[i];
+        if (mark) {
+            int32_t *mcl = mclist_of(S, seq);
+            for (unsigned int k = threadIdx.x; k < mcb.count; k += kAllocThreads) mcl[mcb.base + k] = mcb.item[k];
         }
         if (s + 1 < n_samples) {  // start a new collection
             for (int i = threadIdx.x; i < kSetSlots; i += kAllocThreads) set[i] = kEmpty;
@@ -355,6 +376,8 @@ __device__ __forceinline__ void alloc_tile(const Dev &S, const Frame &fr, const 
         if (threadIdx.x == 0) {
             n_list = 0;
             n_app = 0;
+            n_self = 0;
+            mcb.count = 0;
         }
         __syncthreads();
     }

@@ -2,6 +2,8 @@
 // (diff.hip): device layout of a block-hashed TSDF volume with its MC voxel pool and
 // update log, the per-frame camera constants, and the host-side handle.
 #pragma once
+
+#include <cstddef>
 #include <hip/hip_runtime.h>
 
 #include <array>
@@ -33,14 +35,17 @@ struct StageTimer {
 // space and reports statistics once per workgroup, never once per wave.
 
 struct FrameCounters {
-    unsigned int n_touched;
+    unsigned int n_touched;  // n_touched and n_mc share an aligned 64-bit word: the
+    unsigned int n_mc;       // allocation kernel reserves space in both lists with one atomic
+                             // (n_mc: blocks in the update's MC set, entries of the MC list)
     unsigned int n_new;
-    unsigned int n_mc;  // blocks in the update's MC set (entries of the MC list)
     unsigned int pad;
     unsigned long long voxel_updates;
     unsigned long long log_base;  // log length when the update started; the extraction
                                   // kernel writes the MC list to [log_base, log_base + n_mc)
 };
+
+static_assert(offsetof(FrameCounters, n_mc) == 4 && alignof(FrameCounters) == 8, "shared 64-bit counter word");
 
 struct Counters {
     FrameCounters fc[kRing];
