@@ -609,15 +609,25 @@ __device__ __forceinline__ void mc_block(const Dev &S, int32_t pool, uint64_t ke
     const int x = lane & 7, y = lane >> 3;
     int32_t bx, by, bz;
     unpack_key(key, bx, by, bz);
-    // lane e in 1..7 finds neighbour B + (e & 1, e >> 1 & 1, e >> 2 & 1)
+    // lane e in 1..7 finds neighbour B + (e & 1, e >> 1 & 1, e >> 2 & 1); each probe step
+    // reads the slot's key and value together
     int32_t nb = pool;
     if (lane >= 1 && lane < 8) {
         nb = -1;
         const int32_t nx = bx + (lane & 1), ny = by + ((lane >> 1) & 1), nz = bz + ((lane >> 2) & 1);
         if (key_ok(nx, ny, nz)) {
             const uint64_t nk = pack_key(nx, ny, nz);
-            const int64_t ps = probe_locate(S.T, S.mask, nk, home_slot(nx, ny, nz, nk, S.kind, S.mask));
-            if (ps >= 0) nb = S.T[ps].val;
+            uint64_t p = home_slot(nx, ny, nz, nk, S.kind, S.mask);
+            for (uint64_t m = 0; m <= S.mask; ++m) {
+                const uint64_t k = ld_key(S.T + p);
+                const int32_t v = __hip_atomic_load(&S.T[p].val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (k == nk) {
+                    nb = v;
+                    break;
+                }
+                if (k == kEmpty) break;
+                p = (p + 1) & S.mask;
+            }
         }
     }
     int32_t nbs[8];
@@ -689,13 +699,21 @@ __device__ __forceinline__ void extract_wg(const Dev &S, int seq, int n_partials
     const int lane = lane_id();
     const int64_t gw = wg * kWaves + (threadIdx.x >> 6);
     const int64_t nw = n_wg * kWaves;
+    const int32_t *ml = mclist_of(S, seq);
+    // each list entry and its key are fetched one block ahead
+    int32_t pool = gw < n ? ml[gw] : 0;
+    uint64_t key = gw < n ? S.pool_key[pool] : 0ull;
     for (int64_t t = gw; t < n; t += nw) {
-        const int32_t pool = mclist_of(S, seq)[t];
-        if (lane_id() == 0 && log_base + t < S.log_cap) S.log[log_base + t] = (uint64_t(frame) << 32) | uint32_t(pool);
+        const int64_t tn = t + nw;
+        const int32_t npool = tn < n ? ml[tn] : 0;
+        if (lane == 0 && log_base + t < S.log_cap) S.log[log_base + t] = (uint64_t(frame) << 32) | uint32_t(pool);
         uint32_t out[8];
-        mc_block(S, pool, S.pool_key[pool], out);
+        mc_block(S, pool, key, out);
+        const uint64_t nkey = tn < n ? S.pool_key[npool] : 0ull;
 #pragma unroll
         for (int j = 0; j < 8; ++j) S.MCV[int64_t(pool) * 512 + lane + 64 * j] = out[j];
+        pool = npool;
+        key = nkey;
     }
 }
 
