@@ -461,7 +461,36 @@ def large_batch_bench(vbh, vs=0.003, wall=3.9):
     S.close()
     del keys, depth, rgb
     torch.cuda.empty_cache()
+    out["stream_ceiling"] = stream_ceiling(out["integrate"]["algorithmic_bytes"])
     return out
+
+
+def stream_ceiling(nbytes, reps=5):
+    """What plain streaming kernels (PyTorch's own, not this library's) reach over a working
+    set of the large-batch integration's size: an in-place add (every byte read and
+    written back, the integration's access pattern) and a copy, in GB/s of read plus
+    written bytes, median of `reps`."""
+    import numpy as np
+    import torch
+    n = int(nbytes / 2) // 4
+    a = torch.zeros(n, dtype=torch.int32, device="cuda")
+    b = torch.zeros(n, dtype=torch.int32, device="cuda")
+    res = {"bytes_each": 4 * n}
+    for name, fn in (("inplace_add", lambda: a.add_(1)), ("copy", lambda: b.copy_(a))):
+        fn()
+        times = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        res[name + "_GBps"] = 2 * 4 * n / (float(np.median(times)) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    log(f"[bench] stream ceiling: {res}")
+    return res
 
 
 SERVE_MODES = {0: "rounds", 1: "persistent"}
