@@ -30,7 +30,7 @@
 #include <thread>
 #include <vector>
 
-#include "arena.hpp"
+#include "sched.hpp"
 #include "scene.hpp"
 
 using namespace vbh;
@@ -54,8 +54,8 @@ struct SvReq {
     int64_t off_keys;    // int32 [limit][3]
     int64_t off_mc;      // uint32 [limit][512]
     int64_t off_meta;    // int64 count, uint64 next cursor
-    int32_t *keys_out;   // persistent form: the caller's result buffers (written directly;
-    uint32_t *mc_out;    // NULL: the arena slices above)
+    int32_t *keys_out;   // the caller's result buffers, written directly by the gather
+    uint32_t *mc_out;    // (NULL: the arena slices above)
 };
 
 struct SvRound {
@@ -417,7 +417,7 @@ struct vbh_server {
     vbh_scene *scene = nullptr;
     vbh_server_config cfg{};
     char *arena = nullptr;
-    Arena alloc;
+    Admission adm;  // client queues, cursors, result slots and arena ranges
     std::vector<hipStream_t> streams;
     hipStream_t istream = nullptr;
     SvReq *d_desc = nullptr;    // [max_inflight][max_batch] device descriptors, one row per round
@@ -425,7 +425,6 @@ struct vbh_server {
                                 // round completed, so its upload has been consumed)
     int64_t *h_meta = nullptr;  // pinned [max_inflight][2] results copied back
     unsigned long long *d_len = nullptr, *h_len = nullptr;
-    std::vector<uint64_t> cursor;  // per client
     uint64_t end_v = 0;            // log end of the published version
     uint32_t version = 0;
     // persistent form
@@ -438,24 +437,31 @@ struct vbh_server {
 
 namespace {
 
-struct InFlight {
-    int64_t req;
-    int64_t off, bytes;
-    int slot;
-};
-
 struct RoundRec {
     hipEvent_t ev;
     int stream;
     int row;  // descriptor row
-    std::vector<InFlight> items;
+    std::vector<Admitted> items;
 };
 
 double secs(Clock::time_point t0) { return std::chrono::duration<double>(Clock::now() - t0).count(); }
 
-int64_t req_bytes(int64_t limit, int64_t n_chunks) {
-    auto al = [](int64_t n) { return (n + 255) & ~int64_t(255); };
-    return al(limit * 4) + al(n_chunks * 8) + al(limit * 12) + al(limit * 2048) + 256;
+// The device descriptor of an admitted request: its arena range split into the selected
+// pool indices, chunk counts, keys, MC voxels and count / next cursor (req_bytes' layout).
+void fill_req(SvReq &q, const Admitted &a, const vbh_request &r, int64_t chunk_base, int64_t item_base) {
+    q.cursor = a.cursor;
+    q.end = a.end;
+    q.limit = a.limit;
+    q.chunk_base = chunk_base;
+    q.n_chunks = a.n_chunks;
+    q.item_base = item_base;
+    q.off_sel = a.off;
+    q.off_cnt = q.off_sel + align256(a.limit * 4);
+    q.off_keys = q.off_cnt + align256(a.n_chunks * 8);
+    q.off_mc = q.off_keys + align256(a.limit * 12);
+    q.off_meta = q.off_mc + align256(a.limit * 2048);
+    q.keys_out = r.d_keys_out;
+    q.mc_out = reinterpret_cast<uint32_t *>(r.d_mc_out);
 }
 
 int read_log_end(vbh_server *v, hipStream_t st, uint64_t *out) {
@@ -478,15 +484,13 @@ int run_persistent(vbh_server *v, const vbh_request *reqs, int64_t n_req, const 
     hipStream_t st = v->streams[0];
     const int teams = std::min(v->cfg.n_streams, kMaxTeams);
     const long long ticks_idle = 10 * v->ticks_per_s, ticks_step = 5 * v->ticks_per_s;
-    const int64_t cap_chunks_per_req = (sc->p.log_capacity + kSvChunk - 1) / kSvChunk + 1;
     struct Batch {
         unsigned long long seq;
-        std::vector<InFlight> items;
+        std::vector<Admitted> items;
     };
-    std::vector<std::deque<int64_t>> queue(size_t(v->cfg.n_clients));
-    std::vector<char> busy(size_t(v->cfg.n_clients), 0);
-    std::vector<int> free_slots;
-    for (int i = v->cfg.max_inflight - 1; i >= 0; --i) free_slots.push_back(i);
+    Admission &adm = v->adm;
+    std::vector<Admitted> admitted;
+    std::vector<int64_t> rejected;
     std::deque<Batch> inflight;
     bool running = false;
     unsigned long long published = 0;
@@ -495,17 +499,13 @@ int run_persistent(vbh_server *v, const vbh_request *reqs, int64_t n_req, const 
 
     auto finish = [&](Batch &bt, int slot, double tdone) {
         for (size_t i = 0; i < bt.items.size(); ++i) {
-            const InFlight &f = bt.items[i];
+            const Admitted &f = bt.items[i];
             vbh_request_result &r = res[f.req];
             r.count = H->meta[slot][i][0];
             r.cursor_out = uint64_t(H->meta[slot][i][1]);
             r.done_s = tdone;
             r.status = VBH_OK;
-            const int c = reqs[f.req].client;
-            v->cursor[size_t(c)] = r.cursor_out;
-            busy[size_t(c)] = 0;
-            v->alloc.release(f.off, f.bytes);
-            free_slots.push_back(f.slot);
+            adm.complete(f, r.cursor_out);
             ++n_done;
         }
     };
@@ -557,7 +557,7 @@ int run_persistent(vbh_server *v, const vbh_request *reqs, int64_t n_req, const 
     while (n_done < n_req && rc == VBH_OK) {
         const double now = secs(t0);
         while (next_arrival < n_req && reqs[next_arrival].arrival_s <= now) {
-            queue[size_t(reqs[next_arrival].client)].push_back(next_arrival);
+            adm.arrive(reqs[next_arrival].client, next_arrival, reqs[next_arrival].limit);
             ++next_arrival;
         }
         if (fi < n_frames && frames[fi].time_s <= now) {  // a new scene version
@@ -569,9 +569,7 @@ int run_persistent(vbh_server *v, const vbh_request *reqs, int64_t n_req, const 
         // admit one batch into a free ring slot (a stopped launch is restarted first, since a
         // new launch numbers its batches from 0)
         if (!running) {
-            bool work = false;
-            for (int c = 0; c < v->cfg.n_clients && !work; ++c) work = !busy[size_t(c)] && !queue[size_t(c)].empty();
-            if (work) rc = launch();
+            if (adm.work_pending()) rc = launch();
             if (rc != VBH_OK) break;
         }
         const int slot = int(published % kPRing);
@@ -582,47 +580,20 @@ int run_persistent(vbh_server *v, const vbh_request *reqs, int64_t n_req, const 
             Batch bt;
             bt.seq = published;
             int64_t chunks = 0, items = 0;
-            for (int c = 0; c < v->cfg.n_clients && int(bt.items.size()) < v->cfg.max_batch; ++c) {
-                if (busy[size_t(c)] || queue[size_t(c)].empty() || free_slots.empty()) continue;
-                const int64_t ri = queue[size_t(c)].front();
-                const uint64_t cur = v->cursor[size_t(c)];
-                const int64_t lim = reqs[ri].limit;
-                const int64_t nch = cur < v->end_v ? int64_t((v->end_v - cur + kSvChunk - 1) / kSvChunk) : 0;
-                const int64_t bytes = req_bytes(lim, nch);
-                if (nch > cap_chunks_per_req || bytes > v->cfg.arena_bytes) {
-                    res[ri].status = VBH_EINVAL;  // can never fit
-                    queue[size_t(c)].pop_front();
-                    ++n_done;
-                    continue;
-                }
-                const int64_t off = v->alloc.alloc(bytes);
-                if (off < 0) continue;  // admitted later, when memory frees up
-                queue[size_t(c)].pop_front();
-                busy[size_t(c)] = 1;
-                const int rs = free_slots.back();
-                free_slots.pop_back();
-                SvReq &q = B.req[bt.items.size()];
-                auto al = [](int64_t n) { return (n + 255) & ~int64_t(255); };
-                q.cursor = cur;
-                q.end = v->end_v;
-                q.limit = lim;
-                q.chunk_base = chunks;
-                q.n_chunks = nch;
-                q.item_base = items;
-                q.off_sel = off;
-                q.off_cnt = q.off_sel + al(lim * 4);
-                q.off_keys = q.off_cnt + al(nch * 8);
-                q.off_mc = q.off_keys + al(lim * 12);
-                q.off_meta = q.off_mc + al(lim * 2048);
-                q.keys_out = reqs[ri].d_keys_out;
-                q.mc_out = reinterpret_cast<uint32_t *>(reqs[ri].d_mc_out);
-                chunks += nch;
-                items += lim;
-                res[ri].arrival_s = reqs[ri].arrival_s;
-                res[ri].admit_s = now;
-                res[ri].cursor_in = cur;
-                res[ri].version = v->version;
-                bt.items.push_back({ri, off, bytes, rs});
+            adm.build(v->end_v, admitted, rejected);
+            for (const int64_t ri : rejected) {
+                res[ri].status = VBH_EINVAL;  // can never fit
+                ++n_done;
+            }
+            for (const Admitted &a : admitted) {
+                fill_req(B.req[bt.items.size()], a, reqs[a.req], chunks, items);
+                chunks += a.n_chunks;
+                items += a.limit;
+                res[a.req].arrival_s = reqs[a.req].arrival_s;
+                res[a.req].admit_s = now;
+                res[a.req].cursor_in = a.cursor;
+                res[a.req].version = v->version;
+                bt.items.push_back(a);
             }
             if (!bt.items.empty()) {
                 B.n = int32_t(bt.items.size());
@@ -637,11 +608,9 @@ int run_persistent(vbh_server *v, const vbh_request *reqs, int64_t n_req, const 
         if (running && !inflight.empty() && hipStreamQuery(st) != hipErrorNotReady) rc = VBH_EHIP;  // the launch left
         // idle: nothing in flight or queued and the next event is not imminent
         if (running && inflight.empty()) {
-            bool queued = false;
-            for (const auto &q : queue) queued = queued || !q.empty();
             const double next = std::min(next_arrival < n_req ? reqs[next_arrival].arrival_s : 1e300,
                                          fi < n_frames ? frames[fi].time_s : 1e300);
-            if (!queued && next - now > 0.5) rc = stop();
+            if (!adm.any_queued() && next - now > 0.5) rc = stop();
         }
         std::this_thread::yield();
     }
@@ -670,7 +639,6 @@ int vbh_server_create(vbh_scene *scene, const vbh_server_config *cfg, vbh_server
     if (!v) return VBH_ENOMEM;
     v->scene = scene;
     v->cfg = *cfg;
-    v->cursor.assign(size_t(cfg->n_clients), 0);
     bool ok = hipMalloc(&v->arena, size_t(cfg->arena_bytes)) == hipSuccess &&
               hipMalloc(&v->d_desc, sizeof(SvReq) * size_t(cfg->max_batch) * cfg->max_inflight) == hipSuccess &&
               hipHostMalloc(&v->h_desc, sizeof(SvReq) * size_t(cfg->max_batch) * cfg->max_inflight) == hipSuccess &&
@@ -700,7 +668,8 @@ int vbh_server_create(vbh_scene *scene, const vbh_server_config *cfg, vbh_server
         vbh_server_destroy(v);
         return VBH_ENOMEM;
     }
-    v->alloc.init(cfg->arena_bytes);
+    v->adm.init(cfg->n_clients, cfg->max_inflight, cfg->max_batch, cfg->arena_bytes, kSvChunk,
+                (scene->p.log_capacity + kSvChunk - 1) / kSvChunk + 1);
     if (read_log_end(v, v->istream, &v->end_v) != VBH_OK) {
         vbh_server_destroy(v);
         return VBH_EHIP;
@@ -733,13 +702,13 @@ void vbh_server_destroy(vbh_server *v) {
 
 int vbh_server_set_cursor(vbh_server *v, int32_t client, uint64_t cursor) {
     if (!v || client < 0 || client >= v->cfg.n_clients) return VBH_EINVAL;
-    v->cursor[size_t(client)] = cursor;
+    v->adm.set_cursor(client, cursor);
     return VBH_OK;
 }
 
 int vbh_server_get_cursor(vbh_server *v, int32_t client, uint64_t *cursor) {
     if (!v || !cursor || client < 0 || client >= v->cfg.n_clients) return VBH_EINVAL;
-    *cursor = v->cursor[size_t(client)];
+    *cursor = v->adm.cursor(client);
     return VBH_OK;
 }
 
@@ -759,6 +728,7 @@ int vbh_server_run(vbh_server *v, const vbh_request *reqs, int64_t n_req, const 
     // written or reset blocks): serve from its state now.
     if (read_log_end(v, v->istream, &v->end_v) != VBH_OK) return VBH_EHIP;
     v->version = sc->last_frame;
+    v->adm.begin_run();
     const auto t0 = Clock::now();
     if (v->cfg.mode == VBH_SERVE_PERSISTENT) return run_persistent(v, reqs, n_req, frames, n_frames, res, t0);
     // --- gate between serving and the MC update of fused frames
@@ -811,24 +781,20 @@ int vbh_server_run(vbh_server *v, const vbh_request *reqs, int64_t n_req, const 
     });
 
     // --- scheduler (this thread)
-    std::vector<std::deque<int64_t>> queue(size_t(v->cfg.n_clients));
-    std::vector<char> busy(size_t(v->cfg.n_clients), 0);
-    std::vector<int> free_slots, free_rows;
-    for (int i = v->cfg.max_inflight - 1; i >= 0; --i) {
-        free_slots.push_back(i);
-        free_rows.push_back(i);
-    }
+    Admission &adm = v->adm;
+    std::vector<Admitted> admitted;
+    std::vector<int64_t> rejected;
+    std::vector<int> free_rows;
+    for (int i = v->cfg.max_inflight - 1; i >= 0; --i) free_rows.push_back(i);
     std::deque<RoundRec> rounds;
-    std::vector<std::vector<RoundRec>> dummy;
     std::vector<hipEvent_t> ev_pool;
     int64_t next_arrival = 0, n_done = 0;
     int next_stream = 0;
     int rc_all = VBH_OK;
-    const int64_t cap_chunks_per_req = (sc->p.log_capacity + kSvChunk - 1) / kSvChunk + 1;
     while (n_done < n_req && rc_all == VBH_OK) {
         const double now = secs(t0);
         while (next_arrival < n_req && reqs[next_arrival].arrival_s <= now) {
-            queue[size_t(reqs[next_arrival].client)].push_back(next_arrival);
+            adm.arrive(reqs[next_arrival].client, next_arrival, reqs[next_arrival].limit);
             ++next_arrival;
         }
         bool gate = false;
@@ -853,45 +819,20 @@ int vbh_server_run(vbh_server *v, const vbh_request *reqs, int64_t n_req, const 
             rr.stream = si;
             rr.row = row;
             int64_t chunks = 0, items = 0;
-            for (int c = 0; c < v->cfg.n_clients && int(rr.items.size()) < v->cfg.max_batch; ++c) {
-                if (busy[size_t(c)] || queue[size_t(c)].empty() || free_slots.empty()) continue;
-                const int64_t ri = queue[size_t(c)].front();
-                const uint64_t cur = v->cursor[size_t(c)];
-                const int64_t lim = reqs[ri].limit;
-                const int64_t nch = cur < end_v ? int64_t((end_v - cur + kSvChunk - 1) / kSvChunk) : 0;
-                const int64_t bytes = req_bytes(lim, nch);
-                if (nch > cap_chunks_per_req || bytes > v->cfg.arena_bytes) {
-                    res[ri].status = VBH_EINVAL;  // can never fit
-                    queue[size_t(c)].pop_front();
-                    ++n_done;
-                    continue;
-                }
-                const int64_t off = v->alloc.alloc(bytes);
-                if (off < 0) continue;  // admitted later, when memory frees up
-                queue[size_t(c)].pop_front();
-                busy[size_t(c)] = 1;
-                const int slot = free_slots.back();
-                free_slots.pop_back();
-                SvReq &q = hd[rr.items.size()];
-                auto al = [](int64_t n) { return (n + 255) & ~int64_t(255); };
-                q.cursor = cur;
-                q.end = end_v;
-                q.limit = lim;
-                q.chunk_base = chunks;
-                q.n_chunks = nch;
-                q.item_base = items;
-                q.off_sel = off;
-                q.off_cnt = q.off_sel + al(lim * 4);
-                q.off_keys = q.off_cnt + al(nch * 8);
-                q.off_mc = q.off_keys + al(lim * 12);
-                q.off_meta = q.off_mc + al(lim * 2048);
-                chunks += nch;
-                items += lim;
-                res[ri].arrival_s = reqs[ri].arrival_s;
-                res[ri].admit_s = now;
-                res[ri].cursor_in = cur;
-                res[ri].version = ver;
-                rr.items.push_back({ri, off, bytes, slot});
+            adm.build(end_v, admitted, rejected);
+            for (const int64_t ri : rejected) {
+                res[ri].status = VBH_EINVAL;  // can never fit
+                ++n_done;
+            }
+            for (const Admitted &a : admitted) {
+                fill_req(hd[rr.items.size()], a, reqs[a.req], chunks, items);
+                chunks += a.n_chunks;
+                items += a.limit;
+                res[a.req].arrival_s = reqs[a.req].arrival_s;
+                res[a.req].admit_s = now;
+                res[a.req].cursor_in = a.cursor;
+                res[a.req].version = ver;
+                rr.items.push_back(a);
             }
             if (!rr.items.empty()) {
                 free_rows.pop_back();
@@ -908,18 +849,9 @@ int vbh_server_run(vbh_server *v, const vbh_request *reqs, int64_t n_req, const 
                 if (chunks > 0) k_sv_emit<<<gc, kSvWG, 0, st>>>(sc->d, R);
                 if (items > 0) k_sv_gather<<<gg, kSvWG, 0, st>>>(sc->d, R);
                 e |= hipGetLastError() != hipSuccess;
-                for (int i = 0; i < n; ++i) {
-                    const InFlight &f = rr.items[size_t(i)];
-                    const vbh_request &q = reqs[f.req];
-                    e |= hipMemcpyAsync(v->h_meta + 2 * f.slot, v->arena + hd[i].off_meta, 16, hipMemcpyDeviceToHost,
-                                        st) != hipSuccess;
-                    if (q.d_keys_out && q.limit > 0)
-                        e |= hipMemcpyAsync(q.d_keys_out, v->arena + hd[i].off_keys, size_t(q.limit) * 12,
-                                            hipMemcpyDeviceToDevice, st) != hipSuccess;
-                    if (q.d_mc_out && q.limit > 0)
-                        e |= hipMemcpyAsync(q.d_mc_out, v->arena + hd[i].off_mc, size_t(q.limit) * 2048,
-                                            hipMemcpyDeviceToDevice, st) != hipSuccess;
-                }
+                for (int i = 0; i < n; ++i)
+                    e |= hipMemcpyAsync(v->h_meta + 2 * rr.items[size_t(i)].slot, v->arena + hd[i].off_meta, 16,
+                                        hipMemcpyDeviceToHost, st) != hipSuccess;
                 if (ev_pool.empty()) {
                     hipEvent_t ev;
                     e |= hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess;
@@ -948,18 +880,14 @@ int vbh_server_run(vbh_server *v, const vbh_request *reqs, int64_t n_req, const 
                 break;
             }
             const double tdone = secs(t0);
-            for (const InFlight &f : it->items) {
+            for (const Admitted &f : it->items) {
                 const int64_t *m = v->h_meta + 2 * f.slot;
                 vbh_request_result &r = res[f.req];
                 r.count = m[0];
                 r.cursor_out = uint64_t(m[1]);
                 r.done_s = tdone;
                 r.status = VBH_OK;
-                const int c = reqs[f.req].client;
-                v->cursor[size_t(c)] = r.cursor_out;
-                busy[size_t(c)] = 0;
-                v->alloc.release(f.off, f.bytes);
-                free_slots.push_back(f.slot);
+                adm.complete(f, r.cursor_out);
                 ++n_done;
             }
             ev_pool.push_back(it->ev);

@@ -1,0 +1,231 @@
+"""Host logic of the serving loop: the admission of client requests into batches
+(csrc/sched.hpp), which both forms of vbh_server_run use, compiled with the host compiler
+and driven by a randomised executor on the CPU.  The executor stands in for the device:
+batches complete in any order, the log grows between batches (new scene versions), every
+log entry is live, so an answer takes min(limit, entries past its cursor) and moves the
+cursor that far.  Clients reconnect (cursor back to 0) between requests, some requests
+can never fit the arena, and the arena is small enough that admission waits on memory.
+
+Checked at every step, over many seeds and shapes:
+- a batch holds at most max_batch requests, each its client's oldest waiting request, and
+  no client ever has two requests in flight (so each client's requests run in order);
+- every admitted request starts at its client's current cursor (the previous answer's
+  next cursor, or the reconnect cursor);
+- result slots in flight are distinct and at most max_inflight;
+- arena ranges in flight are disjoint, inside the arena, and at least req_bytes long;
+- a request is rejected exactly when it could never fit (more bytes than the arena or more
+  log chunks than the log holds);
+- whenever nothing is in flight and an idle client waits with a request that fits, the
+  next batch admits something (no stall);
+- every request ends, and afterwards the arena is one free range again; a second run on
+  the same object starts from the cursors the first left.
+Mistakes planted in a copy of the header (a busy client admitted, a lost cursor, the
+chunk capacity ignored, ranges never freed, a client's requests out of order) each fail.
+"""
+import os
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+DRIVER = r'''
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <random>
+#include <set>
+#include <vector>
+#include "sched.hpp"
+
+using namespace vbh;
+#define CHECK(c, ...) do { if (!(c)) { printf("FAIL line %d: ", __LINE__); printf(__VA_ARGS__); printf("\n"); return 1; } } while (0)
+
+struct Req { int client; int64_t limit; int state = 0; /* 0 waiting, 1 in flight, 2 done, 3 rejected */ };
+
+int run_once(Admission &adm, std::mt19937_64 &rng, int C, int M, int B, int64_t A, int64_t K, int64_t cap_chunks,
+             int n_req, uint64_t &E, std::vector<uint64_t> &model_cursor) {
+    std::vector<Req> req(static_cast<size_t>(n_req));
+    std::vector<std::vector<int>> order(static_cast<size_t>(C));
+    for (int i = 0; i < n_req; ++i) {
+        req[size_t(i)].client = int(rng() % uint64_t(C));
+        const int kind = int(rng() % 20);
+        req[size_t(i)].limit = kind == 0 ? int64_t(A / 2048 + 1 + rng() % 100) : kind == 1 ? 0 : int64_t(rng() % 400);
+        order[size_t(req[size_t(i)].client)].push_back(i);
+    }
+    adm.begin_run();
+    std::vector<std::vector<Admitted>> flight;
+    std::vector<Admitted> batch;
+    std::vector<int64_t> rejected;
+    int next = 0, done = 0;
+    std::vector<size_t> pos(size_t(C), 0);  // next request of each client in arrival order
+    long guard = 0;
+    while (done < n_req) {
+        CHECK(++guard < 10000000, "no progress");
+        // arrivals
+        const int arrive = int(rng() % 4);
+        for (int k = 0; k < arrive && next < n_req; ++k, ++next) adm.arrive(req[size_t(next)].client, next, req[size_t(next)].limit);
+        // the log grows (a new scene version)
+        if (rng() % 8 == 0) E += rng() % 5000;
+        if (E > uint64_t(cap_chunks + 3) * uint64_t(K)) E = uint64_t(cap_chunks + 3) * uint64_t(K);
+        // a client reconnects between its requests
+        if (rng() % 16 == 0) {
+            const int c = int(rng() % uint64_t(C));
+            if (!adm.busy(c)) {
+                adm.set_cursor(c, 0);
+                model_cursor[size_t(c)] = 0;
+            }
+        }
+        // admission
+        if (flight.size() < 6 && rng() % 3 != 0) {
+            adm.build(E, batch, rejected);
+            CHECK(int(batch.size()) <= B, "batch of %zu", batch.size());
+            for (int64_t r : rejected) {
+                Req &q = req[size_t(r)];
+                CHECK(q.state == 0, "rejected twice");
+                const uint64_t cur = model_cursor[size_t(q.client)];
+                const int64_t nch = cur < E ? int64_t((E - cur + uint64_t(K) - 1) / uint64_t(K)) : 0;
+                CHECK(req_bytes(q.limit, nch) > A || nch > cap_chunks, "rejected a request that fits");
+                CHECK(order[size_t(q.client)][pos[size_t(q.client)]] == r, "rejected out of order");
+                ++pos[size_t(q.client)];
+                q.state = 3;
+                ++done;
+            }
+            std::set<int> clients;
+            for (const Admitted &a : batch) {
+                Req &q = req[size_t(a.req)];
+                CHECK(q.state == 0, "admitted twice");
+                CHECK(a.client == q.client && a.limit == q.limit && a.end == E, "descriptor");
+                CHECK(clients.insert(a.client).second, "client twice in one batch");
+                CHECK(order[size_t(q.client)][pos[size_t(q.client)]] == a.req, "client order");
+                ++pos[size_t(q.client)];
+                CHECK(a.cursor == model_cursor[size_t(q.client)], "cursor %llu vs %llu", (unsigned long long)a.cursor,
+                      (unsigned long long)model_cursor[size_t(q.client)]);
+                const int64_t nch = a.cursor < E ? int64_t((E - a.cursor + uint64_t(K) - 1) / uint64_t(K)) : 0;
+                CHECK(a.n_chunks == nch && a.bytes >= req_bytes(a.limit, nch), "size");
+                CHECK(nch <= cap_chunks && a.bytes <= A, "admitted a request that can never fit");
+                q.state = 1;
+            }
+            if (!batch.empty()) flight.push_back(batch);
+        }
+        // invariants over everything in flight
+        {
+            std::set<int> slots, busyc;
+            std::vector<std::pair<int64_t, int64_t>> rng_;
+            for (const auto &b : flight)
+                for (const Admitted &a : b) {
+                    CHECK(slots.insert(a.slot).second && a.slot >= 0 && a.slot < M, "slot %d", a.slot);
+                    CHECK(busyc.insert(a.client).second, "two in flight for client %d", a.client);
+                    CHECK(a.off >= 0 && a.off + a.bytes <= A, "range outside the arena");
+                    rng_.push_back({a.off, align256(a.bytes)});
+                }
+            std::sort(rng_.begin(), rng_.end());
+            for (size_t i = 1; i < rng_.size(); ++i) CHECK(rng_[i - 1].first + rng_[i - 1].second <= rng_[i].first, "overlap");
+            if (flight.empty()) {
+                // nothing in flight: a waiting head that fits must be admitted by the next build
+                Admission probe = adm;
+                std::vector<Admitted> b2;
+                std::vector<int64_t> r2;
+                probe.build(E, b2, r2);
+                bool fits = false;
+                for (int c = 0; c < C; ++c) {
+                    if (pos[size_t(c)] >= order[size_t(c)].size()) continue;
+                    const int r = order[size_t(c)][pos[size_t(c)]];
+                    if (r >= next) continue;
+                    const uint64_t cur = model_cursor[size_t(c)];
+                    const int64_t nch = cur < E ? int64_t((E - cur + uint64_t(K) - 1) / uint64_t(K)) : 0;
+                    fits = fits || (req_bytes(req[size_t(r)].limit, nch) <= A && nch <= cap_chunks);
+                }
+                CHECK(!fits || !b2.empty(), "stall with nothing in flight");
+            }
+        }
+        // completions in any order
+        if (!flight.empty() && rng() % 2 == 0) {
+            const size_t k = size_t(rng() % flight.size());
+            for (const Admitted &a : flight[k]) {
+                const uint64_t avail = a.cursor < a.end ? a.end - a.cursor : 0;
+                const uint64_t cnt = std::min<uint64_t>(uint64_t(a.limit), avail);
+                const uint64_t out = a.limit == 0 ? a.cursor : (cnt < uint64_t(a.limit) ? a.end : a.cursor + cnt);
+                adm.complete(a, out);
+                model_cursor[size_t(a.client)] = out;
+                req[size_t(a.req)].state = 2;
+                ++done;
+            }
+            flight.erase(flight.begin() + long(k));
+        }
+    }
+    CHECK(flight.empty(), "flight left");
+    CHECK(adm.arena().free_.size() == 1 && adm.arena().free_.begin()->first == 0 &&
+          adm.arena().free_.begin()->second >= A - 255, "arena not whole again");
+    CHECK(adm.free_slots() == M, "slots not all free");
+    for (int c = 0; c < C; ++c) CHECK(adm.cursor(c) == model_cursor[size_t(c)], "cursor kept");
+    return 0;
+}
+
+int main(int argc, char **argv) {
+    const uint64_t seed = strtoull(argv[1], nullptr, 10);
+    const int C = atoi(argv[2]), M = atoi(argv[3]), B = atoi(argv[4]);
+    const int64_t A = atoll(argv[5]);
+    std::mt19937_64 rng(seed);
+    const int64_t K = 2048, cap_chunks = 64;
+    Admission adm;
+    adm.init(C, M, B, A, K, cap_chunks);
+    uint64_t E = 0;
+    std::vector<uint64_t> model_cursor(size_t(C), 0);
+    for (int run = 0; run < 2; ++run)
+        if (run_once(adm, rng, C, M, B, A, K, cap_chunks, 3000, E, model_cursor)) return 1;
+    printf("ok\n");
+    return 0;
+}
+'''
+
+
+@pytest.fixture(scope="module")
+def driver(tmp_path_factory):
+    d = tmp_path_factory.mktemp("sched")
+    src, exe = d / "drv.cpp", d / "drv"
+    src.write_text(DRIVER)
+    subprocess.run(["g++", "-std=c++17", "-O2", "-Wall", "-I", os.path.join(ROOT, "paper_1805_03709_amd", "csrc"),
+                    "-o", str(exe), str(src)], check=True)
+    return str(exe)
+
+
+SHAPES = [(8, 16, 4, 1 << 20), (3, 2, 8, 1 << 19), (64, 64, 16, 1 << 21), (5, 32, 1, 1 << 22)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("seed", range(6))
+def test_admission_invariants(driver, shape, seed):
+    out = subprocess.run([driver, str(seed), *map(str, shape)], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0 and out.stdout.strip() == "ok", out.stdout + out.stderr
+
+
+# Mistakes planted in a copy of the header (on the CPU): each must fail some case.
+PLANTED = {
+    "admits a busy client": ("if (busy_[c] || queue_[c].empty() || slots_.empty()) continue;",
+                             "if (queue_[c].empty() || slots_.empty()) continue;"),
+    "drops the next cursor": ("cursor_[size_t(a.client)] = cursor_out;", ""),
+    "admits past the chunk capacity": ("if (nch > cap_chunks_ || bytes > arena_bytes_) {",
+                                       "if (bytes > arena_bytes_) {"),
+    "never frees the arena": ("arena_.release(a.off, a.bytes);", ""),
+    "serves a client's newest request first": (
+        "const int64_t ri = queue_[c].front().first, lim = queue_[c].front().second;",
+        "const int64_t ri = queue_[c].back().first, lim = queue_[c].back().second;"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(PLANTED))
+def test_planted_mistake_fails(tmp_path, name):
+    old, new = PLANTED[name]
+    csrc = os.path.join(ROOT, "paper_1805_03709_amd", "csrc")
+    hdr = open(os.path.join(csrc, "sched.hpp")).read()
+    assert old in hdr
+    (tmp_path / "sched.hpp").write_text(hdr.replace(old, new))
+    (tmp_path / "arena.hpp").write_text(open(os.path.join(csrc, "arena.hpp")).read())
+    (tmp_path / "drv.cpp").write_text(DRIVER)
+    exe = tmp_path / "drv"
+    subprocess.run(["g++", "-std=c++17", "-O2", "-I", str(tmp_path), "-o", str(exe), str(tmp_path / "drv.cpp")],
+                   check=True)
+    failed = [subprocess.run([str(exe), str(seed), *map(str, shape)], capture_output=True, text=True,
+                             timeout=120).returncode != 0 for seed in range(2) for shape in SHAPES]
+    assert any(failed)
