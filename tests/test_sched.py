@@ -229,3 +229,15 @@ def test_planted_mistake_fails(tmp_path, name):
     failed = [subprocess.run([str(exe), str(seed), *map(str, shape)], capture_output=True, text=True,
                              timeout=120).returncode != 0 for seed in range(2) for shape in SHAPES]
     assert any(failed)
+
+
+def test_admission_under_address_and_undefined_behaviour_sanitizers(tmp_path):
+    """The same executor, built with AddressSanitizer and UndefinedBehaviorSanitizer."""
+    src, exe = tmp_path / "drv.cpp", tmp_path / "drv"
+    src.write_text(DRIVER)
+    subprocess.run(["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                    "-I", os.path.join(ROOT, "paper_1805_03709_amd", "csrc"), "-o", str(exe), str(src)], check=True)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1", UBSAN_OPTIONS="halt_on_error=1")
+    for shape in SHAPES:
+        out = subprocess.run([str(exe), "7", *map(str, shape)], capture_output=True, text=True, timeout=300, env=env)
+        assert out.returncode == 0 and out.stdout.strip() == "ok", out.stdout + out.stderr[-2000:]
