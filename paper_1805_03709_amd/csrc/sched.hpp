@@ -8,8 +8,10 @@
 // arena, or more log chunks than the log has) is rejected.  Both forms of the serving loop
 // (rounds of kernels on streams, and the persistent launch) build their batches here.
 #pragma once
+#include <condition_variable>
 #include <cstdint>
 #include <deque>
+#include <mutex>
 #include <utility>
 #include <vector>
 
@@ -127,6 +129,60 @@ private:
     int max_batch_ = 1;
     int64_t arena_bytes_ = 0, chunk_ = 1, cap_chunks_ = 0;
     Arena arena_;
+};
+
+// The rounds form fuses frames on a thread of its own while batches are served: a frame's
+// MC update rewrites MC voxels and the log that batches in flight read, so the two exclude
+// each other.  The updater asks and waits; the serving side stops admitting while a request
+// stands and grants it once nothing is in flight; the updater publishes the new log end and
+// version under the same lock and lets serving resume.
+class McGate {
+public:
+    // updater: returns once serving has granted (nothing in flight)
+    void acquire() {
+        std::unique_lock<std::mutex> lk(mu_);
+        request_ = true;
+        cv_.wait(lk, [&] { return granted_; });
+    }
+    // updater: `publish` runs under the lock, then serving may resume
+    template <class F>
+    void release(F &&publish) {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            publish();
+            request_ = false;
+            granted_ = false;
+        }
+        cv_.notify_all();
+    }
+    // updater: no more updates (a request still standing is withdrawn)
+    void finish() {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            request_ = false;
+        }
+        cv_.notify_all();
+    }
+    // serving: `read` runs under the lock (the published log end and version); a standing
+    // request is granted when `idle` (nothing in flight).  Returns true while admission is
+    // closed (a request stands, granted or not).
+    template <class F>
+    bool poll(bool idle, F &&read) {
+        bool grant = false, closed;
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            read();
+            closed = request_;
+            if (request_ && !granted_ && idle) grant = granted_ = true;
+        }
+        if (grant) cv_.notify_all();
+        return closed;
+    }
+
+private:
+    std::mutex mu_;
+    std::condition_variable cv_;
+    bool request_ = false, granted_ = false;
 };
 
 }  // namespace vbh

@@ -732,9 +732,7 @@ int vbh_server_run(vbh_server *v, const vbh_request *reqs, int64_t n_req, const 
     const auto t0 = Clock::now();
     if (v->cfg.mode == VBH_SERVE_PERSISTENT) return run_persistent(v, reqs, n_req, frames, n_frames, res, t0);
     // --- gate between serving and the MC update of fused frames
-    std::mutex mu;
-    std::condition_variable cv;
-    bool mc_request = false, mc_granted = false;
+    McGate gate_mc;
     std::atomic<int> int_error{VBH_OK};
     std::atomic<bool> int_done{n_frames == 0};
     std::thread integ([&]() {
@@ -751,33 +749,23 @@ int vbh_server_run(vbh_server *v, const vbh_request *reqs, int64_t n_req, const 
                 int_error = rc;
                 break;
             }
-            {
-                std::unique_lock<std::mutex> lk(mu);
-                mc_request = true;
-                cv.wait(lk, [&] { return mc_granted; });
-            }
+            gate_mc.acquire();
             rc = scene_mc_update(sc, fr.frame_id, v->istream);
             uint64_t end = 0;
             if (rc == VBH_OK) rc = read_log_end(v, v->istream, &end);
-            {
-                std::lock_guard<std::mutex> lk(mu);
+            gate_mc.release([&] {
                 if (rc == VBH_OK) {
                     v->end_v = end;
                     v->version = fr.frame_id;
                 }
-                mc_request = false;
-                mc_granted = false;
-            }
-            cv.notify_all();
+            });
             if (rc != VBH_OK) {
                 int_error = rc;
                 break;
             }
         }
         int_done = true;
-        std::lock_guard<std::mutex> lk(mu);
-        mc_request = false;
-        cv.notify_all();
+        gate_mc.finish();
     });
 
     // --- scheduler (this thread)
@@ -797,19 +785,12 @@ int vbh_server_run(vbh_server *v, const vbh_request *reqs, int64_t n_req, const 
             adm.arrive(reqs[next_arrival].client, next_arrival, reqs[next_arrival].limit);
             ++next_arrival;
         }
-        bool gate = false;
-        uint64_t end_v;
-        uint32_t ver;
-        {
-            std::lock_guard<std::mutex> lk(mu);
-            gate = mc_request;
+        uint64_t end_v = 0;
+        uint32_t ver = 0;
+        const bool gate = gate_mc.poll(rounds.empty(), [&] {
             end_v = v->end_v;
             ver = v->version;
-            if (mc_request && !mc_granted && rounds.empty()) {
-                mc_granted = true;
-                cv.notify_all();
-            }
-        }
+        });
         // admit and launch one round
         if (!gate && !free_rows.empty()) {
             const int si = next_stream;
@@ -899,18 +880,9 @@ int vbh_server_run(vbh_server *v, const vbh_request *reqs, int64_t n_req, const 
     }
     // drain outstanding GPU work and let integration finish its schedule
     for (hipStream_t s : v->streams) (void)hipStreamSynchronize(s);
-    {
-        std::lock_guard<std::mutex> lk(mu);
-        rounds.clear();
-    }
+    rounds.clear();
     while (!int_done) {
-        {
-            std::lock_guard<std::mutex> lk(mu);
-            if (mc_request && !mc_granted) {
-                mc_granted = true;
-                cv.notify_all();
-            }
-        }
+        (void)gate_mc.poll(true, [] {});
         std::this_thread::sleep_for(std::chrono::microseconds(50));
     }
     integ.join();
