@@ -193,6 +193,7 @@ __device__ __forceinline__ void alloc_tile(const Dev &S, const Frame &fr, const 
     const float xn = (float(u) - fr.cx) / fr.fx;
     const float yn = (float(v) - fr.cy) / fr.fy;
     const float bs = 8.0f * fr.vs;
+    const float ybs = refine_rcp(bs, __builtin_amdgcn_rcpf(bs));
     const int n_samples = 2 * fr.m_band + 1;
     uint64_t prev = kEmpty;
     __syncthreads();
@@ -203,14 +204,26 @@ __device__ __forceinline__ void alloc_tile(const Dev &S, const Frame &fr, const 
             uint64_t key = kEmpty;
             if (ok) {
                 const float pc[3] = {lam * xn, lam * yn, lam};
+                float pw[3], q[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    pw[c] = ((fr.P[c * 4 + 0] * pc[0] + fr.P[c * 4 + 1] * pc[1]) + fr.P[c * 4 + 2] * pc[2]) +
+                            fr.P[c * 4 + 3];
+                // wave-uniform: the reciprocal-based quotient unless some sample of the wave has
+                // a world coordinate below its range (the host bounds the coordinates above)
+                const float small = fminf(fminf(fabsf(pw[0]), fabsf(pw[1])), fabsf(pw[2]));
+                if (!fr.fast_bs || __ballot(small < 0x1p-90f) != 0ull) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) q[c] = floorf(pw[c] / bs);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) q[c] = floorf(corrected_quotient(pw[c], bs, ybs));
+                }
                 int32_t B[3];
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    const float pw = ((fr.P[c * 4 + 0] * pc[0] + fr.P[c * 4 + 1] * pc[1]) + fr.P[c * 4 + 2] * pc[2]) +
-                                     fr.P[c * 4 + 3];
-                    const float q = floorf(pw / bs);
-                    if (!(q >= -1048576.0f && q < 1048576.0f)) ok = false;
-                    B[c] = ok ? int32_t(q) : 0;
+                    if (!(q[c] >= -1048576.0f && q[c] < 1048576.0f)) ok = false;
+                    B[c] = ok ? int32_t(q[c]) : 0;
                 }
                 if (ok)
                     key = pack_key(B[0], B[1], B[2]);
@@ -1232,6 +1245,22 @@ Frame make_frame(const vbh_scene *s, const float *pose) {
     }
     const double bound = 1.001 * col * ((double(1 << 23) + 8.0) * double(f.vs) + tmax);
     f.fast_div = int(bound <= 0x1p32 && std::fabs(double(f.fx)) <= 0x1p20 && std::fabs(double(f.fy)) <= 0x1p20);
+    // Allocation divides world coordinates pw of band samples by the block size bs = 8 vs;
+    // the reciprocal-based quotient equals the correctly rounded one for 2^-32 <= bs <= 2^32
+    // and 2^-90 <= |pw| <= 2^32 (the kernel takes the full division for smaller |pw|).  A
+    // sample lies at camera depth at most dmax + mu on a ray with |x/z|, |y/z| at most the
+    // image's extent over the focal lengths.
+    const double bsd = 8.0 * double(f.vs);
+    const double xr = std::max(std::fabs(double(f.cx)), std::fabs(double(f.W) - 1.0 - double(f.cx))) / std::fabs(double(f.fx));
+    const double yr = std::max(std::fabs(double(f.cy)), std::fabs(double(f.H) - 1.0 - double(f.cy))) / std::fabs(double(f.fy));
+    const double pc_max = (double(f.dmax) + 2.0 * double(f.mu) + double(f.vs)) * std::max(1.0, std::max(xr, yr));
+    double pw_max = 0.0;
+    for (int c = 0; c < 3; ++c)
+        pw_max = std::max(pw_max, std::fabs(double(pose[4 * c + 3])) +
+                                      (std::fabs(double(pose[4 * c])) + std::fabs(double(pose[4 * c + 1])) +
+                                       std::fabs(double(pose[4 * c + 2]))) * pc_max);
+    pw_max *= 1.001;
+    f.fast_bs = int(bsd >= 0x1p-32 && bsd <= 0x1p32 && pw_max <= 0x1p32);
     return f;
 }
 }  // namespace vbh

@@ -94,6 +94,7 @@ struct Frame {
     float vs, mu;
     int m_band;
     int fast_div;  // 1: coordinates and focal lengths admit the reciprocal-based quotient
+    int fast_bs;   // 1: band-sample world coordinates and the block size admit it in allocation
 };
 
 // The touched list and MC list of update `seq`: double-buffered, so that the allocation
