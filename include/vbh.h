@@ -122,6 +122,13 @@ int vbh_map_rebuild(vbh_map *m, void *stream);
 int vbh_map_clear(vbh_map *m, void *stream);
 /* Synchronising: first error recorded by kernels since the last call (then cleared). */
 int vbh_map_status(vbh_map *m, void *stream);
+/* Synchronising: *h_size = live keys (vbh_map_size without the tombstone count). */
+int vbh_size(vbh_map *m, int64_t *h_size, void *stream);
+/* Synchronising: the first error recorded since the last call on a map or a scene handle
+ * (the handle's kind is read from its first word; vbh_map_status / vbh_scene_status),
+ * then cleared.  `handle` is a live vbh_map or vbh_scene; NULL, or a handle of another
+ * kind, gives VBH_EINVAL. */
+int vbh_status(void *handle, void *stream);
 /* Measurement helper: the ceiling that the map's compare-and-swaps are compared with.
  * n_ops 64-bit compare-and-swaps (expected 0) at pseudo-random words of d_words
  * (n_words, a power of two, caller-owned device memory, zeroed by the caller); the number
@@ -229,6 +236,12 @@ int vbh_integrate_frames_host(vbh_scene *s, const float *h_depth, const uint8_t 
  * NULL (colour of the voxel, 0 where cut).  Missing blocks yield zeros. */
 int vbh_extract_mc_indices(vbh_scene *s, const int32_t *d_keys, int64_t n, uint8_t *d_mc, uint8_t *d_rgb,
                            void *stream);
+/* The extraction above for every allocated block: up to cap block keys in pool order to
+ * d_keys_out (int32 [cap][3]) and their MC indices (d_mc, uint8 [cap][512]) and colours
+ * (d_rgb, uint8 [cap][512][3] or NULL); *h_count = allocated blocks (may exceed cap).
+ * Synchronising (the count is read back before the extraction is enqueued). */
+int vbh_extract_mc_all(vbh_scene *s, int32_t *d_keys_out, int64_t cap, uint8_t *d_mc, uint8_t *d_rgb,
+                       int64_t *h_count, void *stream);
 /* MC voxels as kept in the MC pool by the last update of each block (same layout). */
 int vbh_stored_mc(vbh_scene *s, const int32_t *d_keys, int64_t n, uint8_t *d_mc, uint8_t *d_rgb, void *stream);
 

@@ -88,6 +88,9 @@ SIGNATURES = {
     "vbh_map_rebuild": ([_V, _V], C.c_int),
     "vbh_map_clear": ([_V, _V], C.c_int),
     "vbh_map_status": ([_V, _V], C.c_int),
+    "vbh_size": ([_V, C.POINTER(_I64), _V], C.c_int),
+    "vbh_status": ([_V, _V], C.c_int),
+    "vbh_extract_mc_all": ([_V, _P, _I64, _P, _P, C.POINTER(_I64), _V], C.c_int),
     "vbh_scene_create": ([C.POINTER(vbh_params), C.POINTER(_V)], C.c_int),
     "vbh_scene_destroy": ([_V], None),
     "vbh_integrate_frame": ([_V, _P, _P, C.POINTER(C.c_float), C.c_uint32, _V], C.c_int),
@@ -254,6 +257,14 @@ class Map:
         _check(lib().vbh_map_size(self.h, C.byref(live), C.byref(tomb), _stream()), "vbh_map_size")
         return live.value, tomb.value
 
+    def vbh_size(self) -> int:
+        n = C.c_int64()
+        _check(lib().vbh_size(self.h, C.byref(n), _stream()), "vbh_size")
+        return n.value
+
+    def vbh_status(self) -> int:
+        return lib().vbh_status(self.h, _stream())
+
     def vbh_map_export(self, device="cuda"):
         live, _ = self.vbh_map_size()
         keys = torch.empty((max(live, 1), 3), dtype=torch.int32, device=device)
@@ -391,6 +402,21 @@ class Scene:
         _check(lib().vbh_extract_mc_indices(self.h, kp, n, _ptr(mc), _ptr(rgb), _stream()),
                "vbh_extract_mc_indices")
         return mc, rgb
+
+    def vbh_extract_mc_all(self, cap, with_rgb=True, device="cuda"):
+        """Every allocated block (up to cap): (keys int32 [m,3], MC uint8 [m,512], RGB or None,
+        allocated count)."""
+        keys = torch.empty((max(cap, 1), 3), dtype=torch.int32, device=device)
+        mc = torch.empty((max(cap, 1), 512), dtype=torch.uint8, device=device)
+        rgb = torch.empty((max(cap, 1), 512, 3), dtype=torch.uint8, device=device) if with_rgb else None
+        n = C.c_int64()
+        _check(lib().vbh_extract_mc_all(self.h, _ptr(keys), cap, _ptr(mc), _ptr(rgb), C.byref(n), _stream()),
+               "vbh_extract_mc_all")
+        m = min(cap, n.value)
+        return keys[:m], mc[:m], (rgb[:m] if rgb is not None else None), n.value
+
+    def vbh_status(self) -> int:
+        return lib().vbh_status(self.h, _stream())
 
     def vbh_stored_mc(self, keys, with_rgb=True):
         kp, n = _keys(keys)

@@ -19,6 +19,9 @@ namespace vbh {
 
 inline hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
 
+// First word of every handle struct: its kind, read by vbh_status.
+constexpr uint32_t kTagMap = 0x4d415048u, kTagScene = 0x53434e45u;
+
 inline bool is_pow2(uint64_t v) { return v && !(v & (v - 1)); }
 
 inline unsigned grid_for(int64_t n, int per_block, unsigned cap = 1u << 30) {

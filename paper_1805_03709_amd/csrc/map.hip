@@ -17,6 +17,7 @@
 using namespace vbh;
 
 struct vbh_map {
+    uint32_t tag = kTagMap;  // handle kind, read by vbh_status
     Slot *table = nullptr;
     uint64_t slots = 0;
     int hash_kind = 0;

@@ -116,6 +116,7 @@ __device__ __forceinline__ bool depth_valid(float d, const Frame &f) {
 
 // Host-side handle of a scene.
 struct vbh_scene {
+    uint32_t tag = vbh::kTagScene;  // handle kind, read by vbh_status
     vbh_params p{};
     int m_band = 0;
     vbh::Dev d{};
