@@ -655,8 +655,12 @@ __device__ __forceinline__ void mc_block(const Dev &S, int32_t pool, uint64_t ke
         const int o = (xx & 7) + 8 * (yy & 7);
         const int32_t pl = e == 0 ? nbs[0] : e == 1 ? nbs[1] : e == 2 ? nbs[2] : nbs[3];
         const int32_t pu = e == 0 ? nbs[4] : e == 1 ? nbs[5] : e == 2 ? nbs[6] : nbs[7];
-        lo[c] = pl >= 0 ? S.SGN[int64_t(pl) * 64 + o] : 0u;
-        hi[c] = pu >= 0 ? S.SGN[int64_t(pu) * 64 + o] : 0u;
+        // unconditional loads (a missing block reads pool block 0) keep the loads of the
+        // eight columns free of branches
+        const uint32_t vl = S.SGN[int64_t(pl >= 0 ? pl : 0) * 64 + o];
+        const uint32_t vu = S.SGN[int64_t(pu >= 0 ? pu : 0) * 64 + o];
+        lo[c] = pl >= 0 ? vl : 0u;
+        hi[c] = pu >= 0 ? vu : 0u;
     }
     uint32_t neg[4], obs[4];  // 9-bit columns, z = 0..8
 #pragma unroll
