@@ -1186,9 +1186,8 @@ void launch(StageTimer *tm, int stage, hipStream_t st, F kern, dim3 grid, dim3 b
 // n_partials: workgroups of the update's integration kernel whose statistics the
 // extraction kernel reduces (0 if none ran).
 int mc_update(vbh_scene *s, uint32_t frame, int seq, hipStream_t st, StageTimer *tm = nullptr, int n_partials = 0) {
-    const unsigned g = unsigned(s->cus) * 8;
     launch(tm, 2, st, k_mc_mark, dim3(unsigned(s->cus) * 2), dim3(kMarkThreads), s->d, frame, seq);
-    launch(tm, 3, st, k_mc_extract, dim3(g), dim3(kBlock), s->d, seq, n_partials, frame);
+    launch(tm, 3, st, k_mc_extract, dim3(s->g_ext), dim3(kBlock), s->d, seq, n_partials, frame);
     VBH_LAUNCHED();
     return VBH_OK;
 }
@@ -1279,12 +1278,11 @@ int scene_fuse(vbh_scene *s, const float *d_depth, const uint8_t *d_rgb, const f
     const Frame fr = make_frame(s, pose);
     const int seq = s->seq;
     StageTimer *tm = timer_for(s, seq);
-    const unsigned g = unsigned(s->cus) * 8;
     launch(tm, 0, st, k_alloc, alloc_grid(s), dim3(kAllocThreads), s->d, fr, d_depth, d_rgb, frame, seq,
            int(with_mc));
-    launch(tm, 1, st, k_integrate, dim3(g), dim3(kBlock), s->d, fr, int(d_rgb != nullptr), seq,
+    launch(tm, 1, st, k_integrate, dim3(s->g_int), dim3(kBlock), s->d, fr, int(d_rgb != nullptr), seq,
            int(tm != nullptr && with_mc));
-    if (with_mc) launch(tm, 3, st, k_mc_extract, dim3(g), dim3(kBlock), s->d, seq, int(g), frame);
+    if (with_mc) launch(tm, 3, st, k_mc_extract, dim3(s->g_ext), dim3(kBlock), s->d, seq, int(s->g_int), frame);
     VBH_LAUNCHED();
     s->seq = seq + 1;
     s->last_frame = frame;
@@ -1363,9 +1361,8 @@ int scene_alloc_only(vbh_scene *s, const float *d_depth, const float *pose, uint
 int scene_mc_update(vbh_scene *s, uint32_t frame, hipStream_t st) {
     const int seq = s->seq - 1;
     if (seq < 0) return VBH_EINVAL;
-    const unsigned g = unsigned(s->cus) * 8;
     k_mc_mark<<<unsigned(s->cus) * 2, kMarkThreads, 0, st>>>(s->d, frame, seq);
-    k_mc_extract<<<g, kBlock, 0, st>>>(s->d, seq, int(g), frame);
+    k_mc_extract<<<s->g_ext, kBlock, 0, st>>>(s->d, seq, int(s->g_int), frame);
     VBH_LAUNCHED();
     return VBH_OK;
 }
@@ -1397,6 +1394,21 @@ int vbh_scene_create(const vbh_params *p, vbh_scene **out) {
     s->p = *p;
     s->m_band = int(floorf(p->trunc / p->voxel_size + 0.5f));
     s->cus = vbh::device_cus();
+    // The per-frame integration and extraction launches have one workgroup per slot that
+    // the device can hold at once: a grid of several partial generations leaves the last
+    // one running on few CUs (for integration, 5 workgroups per CU by its registers).
+    {
+        int n = 0;
+        s->g_int = unsigned(s->cus) *
+                   unsigned(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_integrate, kBlock, 0) == hipSuccess && n > 0
+                                ? n
+                                : 4);
+        n = 0;
+        s->g_ext = unsigned(s->cus) *
+                   unsigned(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_mc_extract, kBlock, 0) == hipSuccess && n > 0
+                                ? n
+                                : 8);
+    }
     const uint64_t P = uint64_t(p->pool_blocks);
     s->max_chunks = (p->log_capacity + kChunk - 1) / kChunk + 1;
     const size_t sizes[] = {p->slots * sizeof(Slot), P * 512 * sizeof(float), P * 512 * 4, P * 512 * 4,
@@ -1472,13 +1484,12 @@ int vbh_integrate_blocks(vbh_scene *s, const int32_t *d_keys, int64_t n, const f
     const Frame fr = make_frame(s, pose_c2w);
     const int seq = s->seq;
     StageTimer *tm = timer_for(s, seq);
-    const unsigned g = unsigned(s->cus) * 8;
     const int64_t hw = int64_t(s->p.width) * s->p.height;
     k_load_claim<<<grid_for(n, kBlock, 8192), kBlock, 0, st>>>(s->d, d_keys, n, frame_id, seq);
     k_pix_pack<<<grid_for(hw, kBlock, 4096), kBlock, 0, st>>>(s->d, hw, d_depth, d_rgb);
     VBH_LAUNCHED();
-    launch(tm, 1, st, k_integrate, dim3(g), dim3(kBlock), s->d, fr, int(d_rgb != nullptr), seq, 0);
-    if (int rc = mc_update(s, frame_id, seq, st, tm, int(g))) return rc;
+    launch(tm, 1, st, k_integrate, dim3(s->g_int), dim3(kBlock), s->d, fr, int(d_rgb != nullptr), seq, 0);
+    if (int rc = mc_update(s, frame_id, seq, st, tm, int(s->g_int))) return rc;
     s->seq = seq + 1;
     s->last_frame = frame_id;
     return VBH_OK;

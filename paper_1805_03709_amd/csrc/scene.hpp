@@ -125,6 +125,8 @@ struct vbh_scene {
     int64_t max_chunks = 0;
     int seq = 0;        // number of updates so far (ring index of the next one)
     int cus = 256;      // compute units of the device the scene lives on
+    unsigned g_int = 0;  // workgroups of the integration launch: as many as are resident at once
+    unsigned g_ext = 0;  // workgroups of the extraction launch, likewise
     uint32_t last_frame = 0;
     void *mem[15] = {};
     int timing_period = 0;  // time the kernels of every n-th update (0: off)
