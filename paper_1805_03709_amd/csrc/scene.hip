@@ -61,7 +61,7 @@ __device__ __forceinline__ void stage_put(StageBuf<CAP> &b, bool put, int32_t v)
     const int leader = __builtin_ctzll(m);
     unsigned int pos = 0;
     if (lane_id() == leader) pos = atomicAdd(&b.count, unsigned(__popcll(m)));
-    pos = __shfl(pos, leader);
+    pos = unsigned(__builtin_amdgcn_readlane(int(pos), leader));
     if (put) b.item[pos + unsigned(lanes_below(m))] = v;
 }
 
@@ -230,9 +230,14 @@ __device__ __forceinline__ void alloc_tile(const Dev &S, const Frame &fr, const 
                 else
                     raise_err(&S.C->err, kErrKeyRange);
             }
-            const uint64_t left = __shfl(key, (lane + 63) & 63);
-            const uint64_t up = __shfl(key, (lane + 56) & 63);
-            const bool dup = key == prev || (lx > 0 && key == left) || (ly > 0 && key == up);
+            // lane - 1 (row_shr:1) and lane - 8 (row_shr:8, within a 16-lane row, so only odd
+            // pixel rows compare with the row above); a filter only: the set removes the rest
+            const uint32_t klo = uint32_t(key), khi = uint32_t(key >> 32);
+            const uint64_t left = uint64_t(uint32_t(__builtin_amdgcn_update_dpp(0, int(klo), 0x111, 0xf, 0xf, false))) |
+                                  uint64_t(uint32_t(__builtin_amdgcn_update_dpp(0, int(khi), 0x111, 0xf, 0xf, false))) << 32;
+            const uint64_t up = uint64_t(uint32_t(__builtin_amdgcn_update_dpp(0, int(klo), 0x118, 0xf, 0xf, false))) |
+                                uint64_t(uint32_t(__builtin_amdgcn_update_dpp(0, int(khi), 0x118, 0xf, 0xf, false))) << 32;
+            const bool dup = key == prev || (lx > 0 && key == left) || ((ly & 1) && key == up);
             prev = ok ? key : kEmpty;
             bool fresh = false;
             if (ok && !dup) {  // insert into the workgroup's set; the inserting thread owns the key
@@ -252,7 +257,7 @@ __device__ __forceinline__ void alloc_tile(const Dev &S, const Frame &fr, const 
                 const int leader = __builtin_ctzll(m);
                 unsigned int p0 = 0;
                 if (lane == leader) p0 = atomicAdd(&n_list, unsigned(__popcll(m)));
-                p0 = __shfl(p0, leader);
+                p0 = unsigned(__builtin_amdgcn_readlane(int(p0), leader));
                 if (fresh) list[p0 + unsigned(lanes_below(m))] = key;
             }
         }
@@ -299,7 +304,12 @@ __device__ __forceinline__ void alloc_tile(const Dev &S, const Frame &fr, const 
             const bool raise = slot >= 0 && !stamp_now;
             const uint32_t old_stamp = raise ? atomicMax(&S.T[slot].stamp, frame) : frame;
             if (cm) {
-                pb = __shfl(pb, __builtin_ctzll(cm)) + (unsigned long long)lanes_below(cm);
+                {
+                    const int cl = __builtin_ctzll(cm);
+                    pb = (unsigned long long)(unsigned(__builtin_amdgcn_readlane(int(pb), cl))) |
+                         (unsigned long long)(unsigned(__builtin_amdgcn_readlane(int(pb >> 32), cl))) << 32;
+                    pb += (unsigned long long)lanes_below(cm);
+                }
                 if (claimed) {
                     if (int64_t(pb) < S.pool_cap) {
                         S.pool_key[pb] = key;
@@ -317,7 +327,7 @@ __device__ __forceinline__ void alloc_tile(const Dev &S, const Frame &fr, const 
                     const int leader = __builtin_ctzll(sm);
                     unsigned int p0 = 0;
                     if (lane == leader) p0 = atomicAdd(&n_self, unsigned(__popcll(sm)));
-                    p0 = __shfl(p0, leader);
+                    p0 = unsigned(__builtin_amdgcn_readlane(int(p0), leader));
                     if (self) self_pool[p0 + unsigned(lanes_below(sm))] = pool;
                 }
             }
@@ -327,7 +337,7 @@ __device__ __forceinline__ void alloc_tile(const Dev &S, const Frame &fr, const 
                 const int leader = __builtin_ctzll(m);
                 unsigned int p0 = 0;
                 if (lane == leader) p0 = atomicAdd(&n_app, unsigned(__popcll(m)));
-                p0 = __shfl(p0, leader);
+                p0 = unsigned(__builtin_amdgcn_readlane(int(p0), leader));
                 if (app) {
                     const unsigned int q = p0 + unsigned(lanes_below(m));
                     appended[q] = slot;
@@ -422,7 +432,16 @@ __device__ __forceinline__ uint64_t first_lane64(uint64_t v) {
 // then the TSDF state of the passing voxels is loaded together; the slot of the wave's
 // next block is fetched while the current one is processed.  Offsets from wave-uniform
 // bases are 32-bit, so the loads take a scalar base plus a vector offset.
-__global__ void __launch_bounds__(kBlock) k_integrate(Dev S, Frame fr, int with_rgb, int seq, int timed) {
+// A float that is integral and finite to int32, saturating (v_cvt_i32_f32 clamps to the
+// int32 range), where a C++ conversion of an out-of-range value is undefined.
+__device__ __forceinline__ int32_t cvt_sat_i32(float x) {
+    int32_t r;
+    asm("v_cvt_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
+template <bool kRgb>
+__global__ void __launch_bounds__(kBlock) k_integrate(Dev S, Frame fr, int seq, int timed) {
     const FrameCounters *fc = &S.C->fc[seq & (kRing - 1)];
     const int64_t n = fc->n_touched;
     if (timed && blockIdx.x == 0 && threadIdx.x == 0) {  // the work of a timed update
@@ -459,19 +478,23 @@ __global__ void __launch_bounds__(kBlock) k_integrate(Dev S, Frame fr, int with_
             pz[j] = pcz;
             pix[j] = -1;
             if (pool >= 0 && pcz > 0.0f) {
-                float qx, qy;
                 if (fr.fast_div && pcz >= 0x1p-32f) {  // one reciprocal for both quotients
                     const float y = refine_rcp(pcz, __builtin_amdgcn_rcpf(pcz));
-                    qx = corrected_quotient(pcx, pcz, y);
-                    qy = corrected_quotient(pcy, pcz, y);
+                    const float qx = corrected_quotient(pcx, pcz, y);
+                    const float qy = corrected_quotient(pcy, pcz, y);
+                    // |pc| <= 2^32, pc_z >= 2^-32 and |fx|, |fy| <= 2^20 keep fu, fv finite, so
+                    // the saturating conversion and one unsigned compare per axis decide
+                    // 0 <= fu < W and 0 <= fv < H
+                    const int32_t iu = cvt_sat_i32(floorf((fr.fx * qx + fr.cx) + 0.5f));
+                    const int32_t iv = cvt_sat_i32(floorf((fr.fy * qy + fr.cy) + 0.5f));
+                    if (uint32_t(iu) < uint32_t(fr.W) && uint32_t(iv) < uint32_t(fr.H))
+                        pix[j] = int32_t(__umul24(uint32_t(iv), uint32_t(fr.W)) + uint32_t(iu));
                 } else {
-                    qx = pcx / pcz;
-                    qy = pcy / pcz;
+                    const float fu = floorf((fr.fx * (pcx / pcz) + fr.cx) + 0.5f);
+                    const float fv = floorf((fr.fy * (pcy / pcz) + fr.cy) + 0.5f);
+                    if (fu >= 0.0f && fu < float(fr.W) && fv >= 0.0f && fv < float(fr.H))
+                        pix[j] = int32_t(__umul24(uint32_t(fv), uint32_t(fr.W)) + uint32_t(fu));
                 }
-                const float fu = floorf((fr.fx * qx + fr.cx) + 0.5f);
-                const float fv = floorf((fr.fy * qy + fr.cy) + 0.5f);
-                if (fu >= 0.0f && fu < float(fr.W) && fv >= 0.0f && fv < float(fr.H))
-                    pix[j] = int32_t(__umul24(uint32_t(fv), uint32_t(fr.W)) + uint32_t(fu));
             }
         }
         // a voxel outside the image reads pixel 0 (any valid address) and is dropped below
@@ -511,20 +534,21 @@ __global__ void __launch_bounds__(kBlock) k_integrate(Dev S, Frame fr, int with_
             const float wf = float(w_old);
             const float inv = __builtin_amdgcn_rcpf(wf + 1.0f);
             Fn[j] = fmaf(wf, F[j], tsdf) * inv;
-            uint32_t out = w_old == 255u ? 255u : w_old + 1u;
-            if (with_rgb) {
-                // c <- floor((W c + c_obs + floor(n/2)) / n).  The numerator plus 1/2 is exact in
-                // float (integers below 2^17, so the fused multiply-add rounds nothing); its
-                // true quotient lies at least 1/(2n) >= 1/512 away from an integer, while the
-                // product with the reciprocal is off by at most 256 * 2^-22, so truncation
-                // gives the exact floor.
-                const float half = float((w_old + 1u) >> 1) + 0.5f;
+            uint32_t out = min(w_old + 1u, 255u);
+            if constexpr (kRgb) {
+                // c <- floor((W c + c_obs + floor(n/2)) / n), taken as the truncation of
+                // fma(W c + c_obs, 1/n, (floor(n/2) + 1/2) / n).  W c + c_obs is an integer
+                // below 2^17, exact in float.  The true value (W c + c_obs + floor(n/2) + 1/2) / n
+                // lies at least 1/(2n) >= 1/512 away from an integer and below 256; the computed
+                // one is off by at most 256 (2^-22 + 2^-23) + 2^-24 < 1/512 (reciprocal, product
+                // and sum errors), so truncation gives the exact floor.
+                const float hinv = (float((w_old + 1u) >> 1) + 0.5f) * inv;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     const float cur_c = float((w[j] >> (8 * (c + 1))) & 0xFFu);
                     const float obs_c = float((rec[j].y >> (8 * c)) & 0xFFu);
-                    const float num = fmaf(wf, cur_c, obs_c + half);
-                    out |= uint32_t(num * inv) << (8 * (c + 1));
+                    const float num = fmaf(wf, cur_c, obs_c);
+                    out |= uint32_t(fmaf(num, inv, hinv)) << (8 * (c + 1));
                 }
             } else {
                 out |= w[j] & 0xFFFFFF00u;
@@ -536,7 +560,6 @@ __global__ void __launch_bounds__(kBlock) k_integrate(Dev S, Frame fr, int with_
             if (ok[j]) {
                 Fb[uint32_t(lane + 64 * j)] = Fn[j];
                 Wb[uint32_t(lane + 64 * j)] = Wn[j];
-                ++updates;
             }
         }
         // updated voxels replace their sign/observed bits (W >= 1 after an update)
@@ -547,6 +570,7 @@ __global__ void __launch_bounds__(kBlock) k_integrate(Dev S, Frame fr, int with_
             bits |= uint32_t(ok[j] && Fn[j] < 0.0f) << j;
             bits |= uint32_t(ok[j] && Fn[j] == Fn[j]) << (8 + j);
         }
+        updates += uint32_t(__popc(upd & 0xFFu));
         if (upd) S.SGN[int64_t(pool) * 64 + lane] = uint16_t((col & ~upd) | bits);
         cur = nxt;
     }
@@ -1233,6 +1257,7 @@ Frame make_frame(const vbh_scene *s, const float *pose) {
     f.H = s->p.height;
     f.dmin = s->p.depth_min;
     f.dmax = s->p.depth_max;
+    f.dlo = std::max(f.dmin, 0x1p-149f);
     f.vs = s->p.voxel_size;
     f.mu = s->p.trunc;
     f.m_band = s->m_band;
@@ -1280,7 +1305,7 @@ int scene_fuse(vbh_scene *s, const float *d_depth, const uint8_t *d_rgb, const f
     StageTimer *tm = timer_for(s, seq);
     launch(tm, 0, st, k_alloc, alloc_grid(s), dim3(kAllocThreads), s->d, fr, d_depth, d_rgb, frame, seq,
            int(with_mc));
-    launch(tm, 1, st, k_integrate, dim3(s->g_int), dim3(kBlock), s->d, fr, int(d_rgb != nullptr), seq,
+    launch(tm, 1, st, d_rgb ? k_integrate<true> : k_integrate<false>, dim3(s->g_int), dim3(kBlock), s->d, fr, seq,
            int(tm != nullptr && with_mc));
     if (with_mc) launch(tm, 3, st, k_mc_extract, dim3(s->g_ext), dim3(kBlock), s->d, seq, int(s->g_int), frame);
     VBH_LAUNCHED();
@@ -1400,7 +1425,7 @@ int vbh_scene_create(const vbh_params *p, vbh_scene **out) {
     {
         int n = 0;
         s->g_int = unsigned(s->cus) *
-                   unsigned(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_integrate, kBlock, 0) == hipSuccess && n > 0
+                   unsigned(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_integrate<true>, kBlock, 0) == hipSuccess && n > 0
                                 ? n
                                 : 4);
         n = 0;
@@ -1488,7 +1513,7 @@ int vbh_integrate_blocks(vbh_scene *s, const int32_t *d_keys, int64_t n, const f
     k_load_claim<<<grid_for(n, kBlock, 8192), kBlock, 0, st>>>(s->d, d_keys, n, frame_id, seq);
     k_pix_pack<<<grid_for(hw, kBlock, 4096), kBlock, 0, st>>>(s->d, hw, d_depth, d_rgb);
     VBH_LAUNCHED();
-    launch(tm, 1, st, k_integrate, dim3(s->g_int), dim3(kBlock), s->d, fr, int(d_rgb != nullptr), seq, 0);
+    launch(tm, 1, st, d_rgb ? k_integrate<true> : k_integrate<false>, dim3(s->g_int), dim3(kBlock), s->d, fr, seq, 0);
     if (int rc = mc_update(s, frame_id, seq, st, tm, int(s->g_int))) return rc;
     s->seq = seq + 1;
     s->last_frame = frame_id;

@@ -91,6 +91,7 @@ struct Frame {
     float fx, fy, cx, cy;
     int W, H;
     float dmin, dmax;
+    float dlo;  // max(dmin, 2^-149): d >= dlo is d > 0 && d >= dmin (NaN fails both)
     float vs, mu;
     int m_band;
     int fast_div;  // 1: coordinates and focal lengths admit the reciprocal-based quotient
@@ -107,9 +108,10 @@ __device__ __forceinline__ int32_t *mclist_of(const Dev &S, int seq) {
     return S.mclist + int64_t(seq & 1) * S.pool_cap;
 }
 
-// The depth validity rule: positive and inside [dmin, dmax] (float32 tests).
+// The depth validity rule: positive and inside [dmin, dmax] (float32 tests; the smallest
+// positive float 2^-149 folds the sign test into the lower bound).
 __device__ __forceinline__ bool depth_valid(float d, const Frame &f) {
-    return d > 0.0f && d >= f.dmin && d <= f.dmax;
+    return d >= f.dlo && d <= f.dmax;
 }
 
 }  // namespace vbh
