@@ -217,6 +217,71 @@ def test_ragged_empty_and_invalid_frames(orc):
     assert np.array_equal(emc.cpu().numpy(), gmc) and np.array_equal(ergb.cpu().numpy(), grgb)
 
 
+def test_world_scaled_by_power_of_two_takes_full_divisions(orc):
+    """Every length (voxel size, truncation, depths, translations) multiplied by 2^30.
+    Scaling by a power of two commutes with float rounding, so the scene must come out
+    identical to the unscaled one (keys, W, colour and MC voxels bit-exact, F scaled
+    exactly by 2^30).  At this scale the host's coordinate bounds exceed 2^32, so
+    integration projects with the full float division and the float pixel test (the
+    unscaled scene takes the reciprocal-based quotient and the integer test), and
+    allocation divides fully in both (the tiny volume has no finite depth_max).  The scaled
+    scene is also checked against the oracle."""
+    vbh = require_gpu()
+    S = 2.0 ** 30
+    _, depth, rgb, poses = configs.tiny_inputs(6)
+    vol = configs.TINY_VOL
+    vol_s = configs.Volume(**{**vol.__dict__, "voxel_size": vol.voxel_size * S, "trunc": vol.trunc * S})
+    poses_s = poses.copy()
+    poses_s[..., 3] *= S
+    depth_s = depth * S
+    G, O = make_pair(vbh, orc, vol, configs.TINY_CAM)
+    Gs, Os = make_pair(vbh, orc, vol_s, configs.TINY_CAM)
+    integrate_both(G, O, depth, rgb, poses, range(6), check_frames=False)
+    integrate_both(Gs, Os, depth_s, rgb, poses_s, range(6))
+    keys, _ = sort_keys(G.vbh_scene_export_blocks().cpu().numpy())
+    assert keyset(keys) == keyset(Gs.vbh_scene_export_blocks())
+    dk = to_dev(keys)
+    F, W, c, _ = (t.cpu().numpy() for t in G.vbh_scene_read_blocks(dk))
+    Fs, Ws, cs, _ = (t.cpu().numpy() for t in Gs.vbh_scene_read_blocks(dk))
+    assert np.array_equal(W, Ws) and np.array_equal(c, cs)
+    assert np.array_equal(F * np.float32(S), Fs)
+    for x, y in zip(G.vbh_stored_mc(dk), Gs.vbh_stored_mc(dk)):
+        assert torch.equal(x, y)
+    st, sts = G.vbh_scene_stats(), Gs.vbh_scene_stats()
+    assert st["total_voxel_updates"] == sts["total_voxel_updates"] and st["log_length"] == sts["log_length"]
+    # against the oracle fed the scaled inputs (F within the scaled tolerance)
+    ok = Os.blocks()
+    assert keyset(ok) == keyset(keys)
+    oF, oW, orgb, _ = Os.read(keys)
+    assert np.array_equal(Ws, oW) and np.array_equal(cs, orgb)
+    err = np.abs(Fs.astype(np.float64) - oF).max()
+    say(f"  {keys.shape[0]} blocks, max|F-F64| {err:.3g} at scale 2^30")
+    assert err <= F_TOL * S
+
+
+def test_zero_world_coordinates_take_the_full_division(orc):
+    """A camera with identity rotation at (0, 0, -0.95) and a principal point on a pixel
+    centre: band samples on the principal column (row) have world x (y) exactly 0, below
+    the range of the reciprocal-based quotient, so their waves take the full division in
+    allocation; a finite depth range keeps the reciprocal path on for the others.  Sets
+    and state against the oracle over two frames (the second revisits every block)."""
+    vbh = require_gpu()
+    from datagen.scenes import render_frames
+    cam = configs.Camera(101, 77, 90.0, 90.0, 50.0, 38.0)
+    vol = configs.Volume(**{**configs.TINY_VOL.__dict__, "depth_min": 0.3, "depth_max": 3.0})
+    scene, _, _, _ = configs.tiny_inputs(1)
+    pose = np.array([[1.0, 0.0, 0.0, 0.0], [0.0, 1.0, 0.0, 0.0], [0.0, 0.0, 1.0, -0.95]])
+    depth, rgb = render_frames(scene, cam, [pose, pose])
+    dn = depth.numpy()
+    assert ((dn[0] >= 0.3) & (dn[0] <= 3.0)).mean() > 0.5
+    assert dn[0, 38, 50] > 0.3 and dn[0, 20, 50] > 0.3 and dn[0, 38, 20] > 0.3
+    G, O = make_pair(vbh, orc, vol, cam)
+    integrate_both(G, O, depth, rgb, [pose, pose], range(2))
+    k2, F2, W2, rgb2, gmc, grgb = compare_state(G, O)
+    assert (W2 == 2).any()
+    mc_on_identical_input(orc, vol, cam, k2, F2, W2, rgb2, gmc, grgb)
+
+
 def same_scene(A, B):
     """Bit-exact equality of two scenes: statistics, last touched/MC sets, block set, voxel
     state, MC voxels and the update log (a multiset per frame, frames in order)."""

@@ -399,3 +399,37 @@ def test_integration_rotated_pose_closed_form(orc):
     assert obs.sum() > 200
     assert (W[obs] == 1).all() and (W[unobs] == 0).all()
     assert np.abs(F[obs] - np.minimum(sdf, mu)[obs]).max() < 1e-6
+
+
+def test_power_of_two_world_scaling_is_exact(orc):
+    """Multiplying every length (voxel size, truncation, depths, translations) by 2^30
+    commutes with float rounding, so the float32 decisions (block keys, pixels, depth and
+    truncation tests) are unchanged and the float64 F scales exactly: same blocks, W,
+    colour, MC voxels and update log, F times 2^30.  A decision that mixed a length with
+    a pure number in float (say an offset added in metres) would break it."""
+    S = 2.0 ** 30
+    _, depth, rgb, poses = configs.tiny_inputs(3)
+    vol = configs.TINY_VOL
+    vol_s = Volume(**{**vol.__dict__, "voxel_size": vol.voxel_size * S, "trunc": vol.trunc * S})
+    poses_s = poses.copy()
+    poses_s[..., 3] *= S
+    A, B = orc.Scene(vol, configs.TINY_CAM), orc.Scene(vol_s, configs.TINY_CAM)
+    for f in range(3):
+        assert A.integrate(depth[f].numpy(), rgb[f].numpy(), poses[f], f + 1) == 0
+        assert B.integrate((depth[f] * S).numpy(), rgb[f].numpy(), poses_s[f], f + 1) == 0
+        assert np.array_equal(np.sort(A.last_touched(), axis=0), np.sort(B.last_touched(), axis=0))
+    ka, kb = A.blocks(), B.blocks()
+    order = np.lexsort(ka.T[::-1])
+    ka = ka[order]
+    assert ka.shape == kb.shape and set(map(tuple, ka.tolist())) == set(map(tuple, kb.tolist()))
+    Fa, Wa, ca, _ = A.read(ka)
+    Fb, Wb, cb, _ = B.read(ka)
+    assert np.array_equal(Wa, Wb) and np.array_equal(ca, cb)
+    assert np.array_equal(Fa * S, Fb)
+    ma, ra = A.stored_mc(ka)
+    mb, rb = B.stored_mc(ka)
+    assert np.array_equal(ma, mb) and np.array_equal(ra, rb)
+    assert A.log_length() == B.log_length()
+    la, lb = A.updated_since(0, 1 << 20), B.updated_since(0, 1 << 20)
+    for x, y in zip(la, lb):
+        assert np.array_equal(np.asarray(x), np.asarray(y))
