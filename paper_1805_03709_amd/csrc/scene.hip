@@ -150,14 +150,44 @@ struct AllocShared {
 __device__ __forceinline__ uint32_t set_hash(uint64_t k) {
     return uint32_t((k * 0x9E3779B97F4A7C15ull) >> 40);
 }
+__device__ __forceinline__ uint32_t set_hash(uint32_t k) { return (k * 0x9E3779B1u) >> 20; }
+
+// The key of a sample from the lane-1 and lane-8 neighbours (DPP row shifts by 1 and 8
+// within 16-lane rows); lanes without such a neighbour in their row read `old`.
+template <int kCtrl>
+__device__ __forceinline__ uint32_t row_shift(uint32_t v) {
+    return uint32_t(__builtin_amdgcn_update_dpp(0, int(v), kCtrl, 0xf, 0xf, false));
+}
+template <int kCtrl>
+__device__ __forceinline__ uint64_t row_shift(uint64_t v) {
+    return uint64_t(row_shift<kCtrl>(uint32_t(v))) | uint64_t(row_shift<kCtrl>(uint32_t(v >> 32))) << 32;
+}
+
+// Block coordinates of a collected key: a 64-bit table key, or with local keys the 10-bit
+// offsets (x << 20 | y << 10 | z) from the frame's base kb.
+__device__ __forceinline__ void collected_coords(uint64_t k, const Frame &, int32_t &x, int32_t &y, int32_t &z) {
+    unpack_key(k, x, y, z);
+}
+__device__ __forceinline__ void collected_coords(uint32_t k, const Frame &fr, int32_t &x, int32_t &y, int32_t &z) {
+    x = int32_t(k >> 20) + fr.kb[0];
+    y = int32_t((k >> 10) & 1023u) + fr.kb[1];
+    z = int32_t(k & 1023u) + fr.kb[2];
+}
 
 // Allocation (and, with mark, MC-set marking) of the 32x16-pixel tile (tx, ty) for update
-// seq.  Called by all kAllocThreads threads of a workgroup.
+// seq.  Called by all kAllocThreads threads of a workgroup.  K is the collected key:
+// uint64_t (table keys), or uint32_t when the host has shown that every band sample's
+// block lies within [kb, kb + 1024) per axis (Frame::local_keys); the LDS set then holds
+// twice as many 4-byte keys in the same bytes and no sample needs the key-range check.
+template <class K>
 __device__ __forceinline__ void alloc_tile(const Dev &S, const Frame &fr, const float *__restrict__ depth,
                                            const uint8_t *__restrict__ rgb, uint32_t frame, int seq, int mark, int tx,
                                            int ty, AllocShared &sh) {
-    unsigned long long *set = sh.set;
-    unsigned long long *list = sh.list;
+    constexpr bool kLocal = sizeof(K) == 4;
+    constexpr K kNone = K(~K(0));
+    constexpr int kSlotsK = kSetSlots * int(8 / sizeof(K));
+    K *set = reinterpret_cast<K *>(sh.set);
+    K *list = reinterpret_cast<K *>(sh.list);
     int32_t *appended = sh.appended;
     uint16_t *app_idx = sh.app_idx;
     int32_t *app_pool = sh.app_pool;
@@ -167,7 +197,7 @@ __device__ __forceinline__ void alloc_tile(const Dev &S, const Frame &fr, const 
     unsigned long long &pool_base = sh.pool_base;
     FrameCounters *fc = &S.C->fc[seq & (kRing - 1)];
     if (tx == 0 && ty == 0 && threadIdx.x == 0) begin_update(S, seq);
-    for (int i = threadIdx.x; i < kSetSlots; i += kAllocThreads) set[i] = kEmpty;
+    for (int i = threadIdx.x; i < kSlotsK; i += kAllocThreads) set[i] = kNone;
     if (threadIdx.x == 0) {
         n_list = 0;
         n_app = 0;
@@ -195,13 +225,13 @@ __device__ __forceinline__ void alloc_tile(const Dev &S, const Frame &fr, const 
     const float bs = 8.0f * fr.vs;
     const float ybs = refine_rcp(bs, __builtin_amdgcn_rcpf(bs));
     const int n_samples = 2 * fr.m_band + 1;
-    uint64_t prev = kEmpty;
+    K prev = kNone;
     __syncthreads();
     for (int s = 0; s < n_samples; ++s) {  // workgroup-uniform
         if (wave_any) {
             const float lam = (d - fr.mu) + float(s) * fr.vs;
             bool ok = valid && lam > 0.0f;
-            uint64_t key = kEmpty;
+            K key = kNone;
             if (ok) {
                 const float pc[3] = {lam * xn, lam * yn, lam};
                 float pw[3], q[3];
@@ -219,47 +249,44 @@ __device__ __forceinline__ void alloc_tile(const Dev &S, const Frame &fr, const 
 #pragma unroll
                     for (int c = 0; c < 3; ++c) q[c] = floorf(corrected_quotient(pw[c], bs, ybs));
                 }
-                int32_t B[3];
+                if constexpr (kLocal) {  // 0 <= q - kb < 1024, exact in float
+                    key = uint32_t(q[0] - fr.kbf[0]) << 20 | uint32_t(q[1] - fr.kbf[1]) << 10 |
+                          uint32_t(q[2] - fr.kbf[2]);
+                } else {
+                    int32_t B[3];
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    if (!(q[c] >= -1048576.0f && q[c] < 1048576.0f)) ok = false;
-                    B[c] = ok ? int32_t(q[c]) : 0;
+                    for (int c = 0; c < 3; ++c) {
+                        if (!(q[c] >= -1048576.0f && q[c] < 1048576.0f)) ok = false;
+                        B[c] = ok ? int32_t(q[c]) : 0;
+                    }
+                    if (ok)
+                        key = pack_key(B[0], B[1], B[2]);
+                    else
+                        raise_err(&S.C->err, kErrKeyRange);
                 }
-                if (ok)
-                    key = pack_key(B[0], B[1], B[2]);
-                else
-                    raise_err(&S.C->err, kErrKeyRange);
             }
             // lane - 1 (row_shr:1) and lane - 8 (row_shr:8, within a 16-lane row, so only odd
             // pixel rows compare with the row above); a filter only: the set removes the rest
-            const uint32_t klo = uint32_t(key), khi = uint32_t(key >> 32);
-            const uint64_t left = uint64_t(uint32_t(__builtin_amdgcn_update_dpp(0, int(klo), 0x111, 0xf, 0xf, false))) |
-                                  uint64_t(uint32_t(__builtin_amdgcn_update_dpp(0, int(khi), 0x111, 0xf, 0xf, false))) << 32;
-            const uint64_t up = uint64_t(uint32_t(__builtin_amdgcn_update_dpp(0, int(klo), 0x118, 0xf, 0xf, false))) |
-                                uint64_t(uint32_t(__builtin_amdgcn_update_dpp(0, int(khi), 0x118, 0xf, 0xf, false))) << 32;
+            const K left = row_shift<0x111>(key);
+            const K up = row_shift<0x118>(key);
             const bool dup = key == prev || (lx > 0 && key == left) || ((ly & 1) && key == up);
-            prev = ok ? key : kEmpty;
+            prev = ok ? key : kNone;
             bool fresh = false;
             if (ok && !dup) {  // insert into the workgroup's set; the inserting thread owns the key
-                uint32_t h = set_hash(key) & (kSetSlots - 1);
-                for (int n = 0; n < kSetSlots; ++n) {
-                    const unsigned long long old = atomicCAS(&set[h], kEmpty, key);
-                    if (old == kEmpty) {
+                uint32_t h = set_hash(key) & uint32_t(kSlotsK - 1);
+                for (int n = 0; n < kSlotsK; ++n) {
+                    const K old = atomicCAS(&set[h], kNone, key);
+                    if (old == kNone) {
                         fresh = true;
                         break;
                     }
                     if (old == key) break;
-                    h = (h + 1) & (kSetSlots - 1);
+                    h = (h + 1) & uint32_t(kSlotsK - 1);
                 }
             }
-            const unsigned long long m = __ballot(fresh);
-            if (m) {
-                const int leader = __builtin_ctzll(m);
-                unsigned int p0 = 0;
-                if (lane == leader) p0 = atomicAdd(&n_list, unsigned(__popcll(m)));
-                p0 = unsigned(__builtin_amdgcn_readlane(int(p0), leader));
-                if (fresh) list[p0 + unsigned(lanes_below(m))] = key;
-            }
+            // the compiler turns the wave's LDS atomics on one address into one atomic and
+            // each lane's rank among the active lanes
+            if (fresh) list[atomicAdd(&n_list, 1u)] = key;
         }
         __syncthreads();
         const unsigned int nl = n_list;
@@ -272,9 +299,9 @@ __device__ __forceinline__ void alloc_tile(const Dev &S, const Frame &fr, const 
             bool claimed = false, stamp_now = false;
             uint64_t key = kEmpty;
             if (i < nl) {
-                key = list[i];
                 int32_t x, y, z;
-                unpack_key(key, x, y, z);
+                collected_coords(list[i], fr, x, y, z);
+                key = pack_key(x, y, z);
                 const uint32_t home = uint32_t(home_slot(x, y, z, key, S.kind, S.mask));
                 const uint64_t first = ld_key(S.T + home);
                 const int32_t hv = __hip_atomic_load(&S.T[home].val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -359,7 +386,7 @@ __device__ __forceinline__ void alloc_tile(const Dev &S, const Frame &fr, const 
                         target = app_pool[b];
                     } else {
                         int32_t x, y, z;
-                        unpack_key(list[app_idx[b]], x, y, z);
+                        collected_coords(list[app_idx[b]], fr, x, y, z);
                         target = negative_neighbour(S, x, y, z, int(e));
                     }
                 } else if (it < items) {
@@ -392,8 +419,8 @@ __device__ __forceinline__ void alloc_tile(const Dev &S, const Frame &fr, const 
             for (unsigned int k = threadIdx.x; k < mcb.count; k += kAllocThreads) mcl[mcb.base + k] = mcb.item[k];
         }
         if (s + 1 < n_samples) {  // start a new collection
-            for (int i = threadIdx.x; i < kSetSlots; i += kAllocThreads) set[i] = kEmpty;
-            prev = kEmpty;
+            for (int i = threadIdx.x; i < kSlotsK; i += kAllocThreads) set[i] = kNone;
+            prev = kNone;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -406,11 +433,12 @@ __device__ __forceinline__ void alloc_tile(const Dev &S, const Frame &fr, const 
     }
 }
 
+template <class K>
 __global__ void __launch_bounds__(kAllocThreads) k_alloc(Dev S, Frame fr, const float *__restrict__ depth,
                                                          const uint8_t *__restrict__ rgb, uint32_t frame, int seq,
                                                          int mark) {
     __shared__ AllocShared sh;
-    alloc_tile(S, fr, depth, rgb, frame, seq, mark, int(blockIdx.x), int(blockIdx.y), sh);
+    alloc_tile<K>(S, fr, depth, rgb, frame, seq, mark, int(blockIdx.x), int(blockIdx.y), sh);
 }
 
 __device__ __forceinline__ uint64_t first_lane64(uint64_t v) {
@@ -1247,7 +1275,7 @@ int keys_of(vbh_scene *s, int which, int32_t *d_keys, int64_t cap, int64_t *h_co
 
 namespace vbh {
 Frame make_frame(const vbh_scene *s, const float *pose) {
-    Frame f;
+    Frame f{};
     std::memcpy(f.P, pose, sizeof(f.P));
     f.fx = s->p.fx;
     f.fy = s->p.fy;
@@ -1289,6 +1317,31 @@ Frame make_frame(const vbh_scene *s, const float *pose) {
                                        std::fabs(double(pose[4 * c + 2]))) * pc_max);
     pw_max *= 1.001;
     f.fast_bs = int(bsd >= 0x1p-32 && bsd <= 0x1p32 && pw_max <= 0x1p32);
+    // Allocation may collect 32-bit keys B - kb (10 bits per axis) when every band sample's
+    // block lies within 1024 blocks of kb = floor(t / bs) - 512: a sample's camera depth is
+    // at most lam_max = dmax - mu + 2 m vs, so |pw_c - t_c| is at most the row sum of |R|
+    // times lam_max max(1, |x/z|, |y/z|), with slack for rounding; the blocks must also lie
+    // inside the key range, so that no sample needs the range check.
+    f.local_keys = 0;
+    const double lam_max = double(f.dmax) + std::fabs(double(f.mu)) + 2.0 * double(f.m_band) * double(f.vs) + double(f.vs);
+    const double reach_pc = lam_max * std::max(1.0, std::max(xr, yr));
+    if (std::isfinite(reach_pc) && std::isfinite(bsd) && bsd > 0.0) {
+        bool ok = true;
+        for (int c = 0; c < 3 && ok; ++c) {
+            const double t = double(pose[4 * c + 3]);
+            const double span = 1.01 * (std::fabs(double(pose[4 * c])) + std::fabs(double(pose[4 * c + 1])) +
+                                        std::fabs(double(pose[4 * c + 2]))) * reach_pc +
+                                0x1p-20 * (std::fabs(t) + 1.0);
+            const double base = std::floor(t / bsd);
+            const double reach = std::ceil(span / bsd) + 3.0;
+            ok = std::isfinite(base) && reach <= 511.0 && std::fabs(base) + reach <= double(1 << 20) - 1.0;
+            if (ok) {
+                f.kb[c] = int(base) - 512;
+                f.kbf[c] = float(f.kb[c]);
+            }
+        }
+        f.local_keys = int(ok);
+    }
     return f;
 }
 }  // namespace vbh
@@ -1303,7 +1356,7 @@ int scene_fuse(vbh_scene *s, const float *d_depth, const uint8_t *d_rgb, const f
     const Frame fr = make_frame(s, pose);
     const int seq = s->seq;
     StageTimer *tm = timer_for(s, seq);
-    launch(tm, 0, st, k_alloc, alloc_grid(s), dim3(kAllocThreads), s->d, fr, d_depth, d_rgb, frame, seq,
+    launch(tm, 0, st, fr.local_keys ? k_alloc<uint32_t> : k_alloc<uint64_t>, alloc_grid(s), dim3(kAllocThreads), s->d, fr, d_depth, d_rgb, frame, seq,
            int(with_mc));
     launch(tm, 1, st, d_rgb ? k_integrate<true> : k_integrate<false>, dim3(s->g_int), dim3(kBlock), s->d, fr, seq,
            int(tm != nullptr && with_mc));
@@ -1375,8 +1428,9 @@ int scene_fuse_frames_host(vbh_scene *s, const float *h_depth, const uint8_t *h_
 
 int scene_alloc_only(vbh_scene *s, const float *d_depth, const float *pose, uint32_t frame, hipStream_t st) {
     const int seq = s->seq;
-    launch(timer_for(s, seq), 0, st, k_alloc, alloc_grid(s), dim3(kAllocThreads), s->d, make_frame(s, pose), d_depth,
-           static_cast<const uint8_t *>(nullptr), frame, seq, 0);
+    const Frame fr = make_frame(s, pose);
+    launch(timer_for(s, seq), 0, st, fr.local_keys ? k_alloc<uint32_t> : k_alloc<uint64_t>, alloc_grid(s),
+           dim3(kAllocThreads), s->d, fr, d_depth, static_cast<const uint8_t *>(nullptr), frame, seq, 0);
     VBH_LAUNCHED();
     s->seq = seq + 1;
     s->last_frame = frame;
