@@ -147,6 +147,20 @@ struct AllocShared {
     unsigned long long pool_base;
 };
 
+// A float that is integral and finite to int32, saturating (v_cvt_i32_f32 clamps to the
+// int32 range), where a C++ conversion of an out-of-range value is undefined.
+__device__ __forceinline__ int32_t cvt_sat_i32(float x) {
+    int32_t r;
+    asm("v_cvt_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+// floor(x) as int32 in one instruction, for x whose floor is known to lie in int32 range.
+__device__ __forceinline__ int32_t cvt_flr_i32(float x) {
+    int32_t r;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
 __device__ __forceinline__ uint32_t set_hash(uint64_t k) {
     return uint32_t((k * 0x9E3779B97F4A7C15ull) >> 40);
 }
@@ -239,20 +253,28 @@ __device__ __forceinline__ void alloc_tile(const Dev &S, const Frame &fr, const 
                 for (int c = 0; c < 3; ++c)
                     pw[c] = ((fr.P[c * 4 + 0] * pc[0] + fr.P[c * 4 + 1] * pc[1]) + fr.P[c * 4 + 2] * pc[2]) +
                             fr.P[c * 4 + 3];
-                // wave-uniform: the reciprocal-based quotient unless some sample of the wave has
-                // a world coordinate below its range (the host bounds the coordinates above)
-                const float small = fminf(fminf(fabsf(pw[0]), fabsf(pw[1])), fabsf(pw[2]));
-                if (!fr.fast_bs || __ballot(small < 0x1p-90f) != 0ull) {
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) q[c] = floorf(pw[c] / bs);
-                } else {
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) q[c] = floorf(corrected_quotient(pw[c], bs, ybs));
+                // wave-uniform: the reciprocal-based quotient (the host bounds the coordinates
+                // above); with fast_bs 1, not for a wave where some sample has a world
+                // coordinate below its range; with fast_bs 2 (bs <= 1) such a coordinate's
+                // quotient still has the floor of the true one, so every wave takes it
+                bool full = fr.fast_bs == 0;
+                if (fr.fast_bs == 1) {
+                    const float small = fminf(fminf(fabsf(pw[0]), fabsf(pw[1])), fabsf(pw[2]));
+                    full = __ballot(small < 0x1p-90f) != 0ull;
                 }
-                if constexpr (kLocal) {  // 0 <= q - kb < 1024, exact in float
-                    key = uint32_t(q[0] - fr.kbf[0]) << 20 | uint32_t(q[1] - fr.kbf[1]) << 10 |
-                          uint32_t(q[2] - fr.kbf[2]);
+                if (full) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) q[c] = pw[c] / bs;
                 } else {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) q[c] = corrected_quotient(pw[c], bs, ybs);
+                }
+                if constexpr (kLocal) {  // 0 <= B - kb < 1024 per axis, B = floor(q): packed in 10 bits
+                    key = ((uint32_t(cvt_flr_i32(q[0])) << 20) + (uint32_t(cvt_flr_i32(q[1])) << 10) +
+                           uint32_t(cvt_flr_i32(q[2]))) - fr.kb_packed;
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) q[c] = floorf(q[c]);
                     int32_t B[3];
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
@@ -460,14 +482,6 @@ __device__ __forceinline__ uint64_t first_lane64(uint64_t v) {
 // then the TSDF state of the passing voxels is loaded together; the slot of the wave's
 // next block is fetched while the current one is processed.  Offsets from wave-uniform
 // bases are 32-bit, so the loads take a scalar base plus a vector offset.
-// A float that is integral and finite to int32, saturating (v_cvt_i32_f32 clamps to the
-// int32 range), where a C++ conversion of an out-of-range value is undefined.
-__device__ __forceinline__ int32_t cvt_sat_i32(float x) {
-    int32_t r;
-    asm("v_cvt_i32_f32 %0, %1" : "=v"(r) : "v"(x));
-    return r;
-}
-
 template <bool kRgb>
 __global__ void __launch_bounds__(kBlock) k_integrate(Dev S, Frame fr, int seq, int timed) {
     const FrameCounters *fc = &S.C->fc[seq & (kRing - 1)];
@@ -1317,6 +1331,10 @@ Frame make_frame(const vbh_scene *s, const float *pose) {
                                        std::fabs(double(pose[4 * c + 2]))) * pc_max);
     pw_max *= 1.001;
     f.fast_bs = int(bsd >= 0x1p-32 && bsd <= 0x1p32 && pw_max <= 0x1p32);
+    // A band sample's coordinate below 2^-90 in magnitude divided by bs <= 1 gives a
+    // nonzero product with the reciprocal (at least 1) of the dividend's sign and below 1
+    // in magnitude, so its floor is that of the true quotient: no fallback is needed.
+    if (f.fast_bs && bsd <= 1.0) f.fast_bs = 2;
     // Allocation may collect 32-bit keys B - kb (10 bits per axis) when every band sample's
     // block lies within 1024 blocks of kb = floor(t / bs) - 512: a sample's camera depth is
     // at most lam_max = dmax - mu + 2 m vs, so |pw_c - t_c| is at most the row sum of |R|
@@ -1335,12 +1353,11 @@ Frame make_frame(const vbh_scene *s, const float *pose) {
             const double base = std::floor(t / bsd);
             const double reach = std::ceil(span / bsd) + 3.0;
             ok = std::isfinite(base) && reach <= 511.0 && std::fabs(base) + reach <= double(1 << 20) - 1.0;
-            if (ok) {
-                f.kb[c] = int(base) - 512;
-                f.kbf[c] = float(f.kb[c]);
-            }
+            if (ok) f.kb[c] = int(base) - 512;
         }
         f.local_keys = int(ok);
+        if (ok)  // (B_x << 20) + (B_y << 10) + B_z - kb_packed, modulo 2^32, packs B - kb
+            f.kb_packed = (uint32_t(f.kb[0]) << 20) + (uint32_t(f.kb[1]) << 10) + uint32_t(f.kb[2]);
     }
     return f;
 }

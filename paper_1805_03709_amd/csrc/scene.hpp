@@ -96,9 +96,10 @@ struct Frame {
     int m_band;
     int fast_div;  // 1: coordinates and focal lengths admit the reciprocal-based quotient
     int fast_bs;   // 1: band-sample world coordinates and the block size admit it in allocation
+                   // (2: also for coordinates below 2^-90, as bs <= 1)
     int local_keys;  // 1: every band sample's block B satisfies 0 <= B - kb < 1024 per axis
     int kb[3];       // base of the allocation's 32-bit tile-local keys (block coordinates)
-    float kbf[3];    // kb as floats
+    uint32_t kb_packed;  // (kb_x << 20) + (kb_y << 10) + kb_z modulo 2^32
 };
 
 // The touched list and MC list of update `seq`: double-buffered, so that the allocation

@@ -10,7 +10,10 @@ and denormal dividends.
   can round a quotient that lies just past a midpoint the wrong way (Markstein's known
   exception).  This is what the check expects; the hardware reciprocal is checked against
   the compiler's division on the GPU (test_gpu_fastdiv).
-- For dividends below 2^-90 the quotient stays below 2^-56 in magnitude."""
+- For dividends below 2^-90 the quotient stays below 2^-56 in magnitude; with a divisor at
+  most 1 (so the reciprocal is at least 1 and a nonzero dividend's product cannot vanish)
+  its floor equals the floor of the true quotient (0 or -1 by the dividend's sign), which
+  is all allocation takes from it."""
 import os
 import subprocess
 
@@ -41,7 +44,19 @@ static float draw(int lo, int hi) {
     float f = std::ldexp(1.0f + float(m) / 8388608.0f, e);
     return (r >> 63) ? -f : f;
 }
-static long long checked = 0, bad = 0, bad_tiny = 0, allones_off = 0;
+static long long checked = 0, bad = 0, bad_tiny = 0, allones_off = 0, bad_floor = 0;
+static void check_floor(float a, float b) {  // |a| < 2^-90, 2^-32 <= b <= 1
+    const float rb = 1.0f / b;
+    for (int k = -1; k <= 1; ++k) {
+        const float y = vbh::refine_rcp(b, bits(ubits(rb) + uint32_t(k)));
+        const float q = vbh::corrected_quotient(a, b, y);
+        ++checked;
+        if (!(std::floor(q) == std::floor(a / b))) {
+            if (bad_floor < 5) printf("floor mismatch a=%a b=%a q=%a want=%a\n", a, b, q, a / b);
+            ++bad_floor;
+        }
+    }
+}
 static void check(float a, float b) {
     const float rb = 1.0f / b;
     const bool allones = (ubits(b) & 0x7FFFFFu) == 0x7FFFFFu;
@@ -86,8 +101,18 @@ int main(int argc, char **argv) {
     check(0x1p32f, 0x1p-32f);
     for (int i = 0; i < 100000; ++i) check(draw(-149, -91), std::fabs(draw(-32, 31)));  // tiny dividends
     for (int i = 1; i < 100000; ++i) check(bits(uint32_t(i)), std::fabs(draw(-32, 31)));  // denormal dividends
-    printf("checked %lld bad %lld bad_tiny %lld allones_off %lld\n", checked, bad, bad_tiny, allones_off);
-    return bad || bad_tiny ? 1 : 0;
+    for (int i = 0; i < 200000; ++i) {  // floors of tiny and denormal dividends, divisors <= 1
+        const float b = (i % 97 == 0) ? 1.0f : std::fabs(draw(-32, -1));
+        const float a = (i & 1) ? draw(-149, -91) : bits(uint32_t(1 + next() % 0x7FFFFFu)) * ((next() & 1) ? -1.0f : 1.0f);
+        check_floor(a, b);
+    }
+    check_floor(0.0f, 0x1p-32f);
+    check_floor(-0.0f, 1.0f);
+    check_floor(-bits(1u), 1.0f);
+    check_floor(bits(1u), 0x1p-32f);
+    printf("checked %lld bad %lld bad_tiny %lld allones_off %lld bad_floor %lld\n", checked, bad, bad_tiny,
+           allones_off, bad_floor);
+    return bad || bad_tiny || bad_floor ? 1 : 0;
 }
 '''
 
@@ -106,4 +131,4 @@ def driver(tmp_path_factory):
 def test_corrected_quotient_is_correctly_rounded(driver):
     out = subprocess.run([driver, "2000000"], capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stdout + out.stderr
-    assert "bad 0 bad_tiny 0" in out.stdout
+    assert "bad 0 bad_tiny 0" in out.stdout and "bad_floor 0" in out.stdout
