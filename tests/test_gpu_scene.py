@@ -4,6 +4,8 @@ Bar: key sets, allocation sets, W and colour bit-exact; F within 1e-5 m of the f
 oracle; MC voxels bit-exact on identical F/W input, and end to end only where some
 corner has |F_oracle| <= 1e-5.
 """
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -279,6 +281,36 @@ def test_zero_world_coordinates_take_the_full_division(orc):
     integrate_both(G, O, depth, rgb, [pose, pose], range(2))
     k2, F2, W2, rgb2, gmc, grgb = compare_state(G, O)
     assert (W2 == 2).any()
+    mc_on_identical_input(orc, vol, cam, k2, F2, W2, rgb2, gmc, grgb)
+
+
+def test_local_keys_at_both_ends_of_their_range(orc):
+    """Allocation's 32-bit local keys hold each block coordinate as an offset in [0, 1024)
+    from a base 512 blocks below the camera's block.  Here 0.5 mm voxels (4 mm blocks), a
+    2 m depth limit and a narrow camera put the host's reach at 510 blocks, just inside the
+    511 it admits, and two views of the far walls 1.95 m away (along +z, then along -z)
+    give z offsets near 999 and near 25.  Sets and state against the oracle."""
+    vbh = require_gpu()
+    from datagen.scenes import render_frames
+    cam = configs.Camera(101, 77, 2000.0, 2000.0, 50.0, 38.0)
+    vol = configs.Volume(slots=1 << 16, pool_blocks=1 << 14, voxel_size=0.0005, trunc=0.002,
+                         depth_min=0.3, depth_max=2.0, log_capacity=1 << 20)
+    # the host's bound (camera depth at most dmax + mu + 2 m vs + vs, identity-like rows)
+    lam = vol.depth_max + vol.trunc + 2 * 4 * vol.voxel_size + vol.voxel_size
+    reach = math.ceil((1.01 * lam + 2.0 ** -20 * 1.95) / (8 * vol.voxel_size)) + 3
+    assert 500 <= reach <= 511
+    scene, _, _, _ = configs.tiny_inputs(1)
+    poses = np.array([[[1.0, 0.0, 0.0, 0.85], [0.0, 1.0, 0.0, 0.85], [0.0, 0.0, 1.0, -0.95]],
+                      [[-1.0, 0.0, 0.0, 0.85], [0.0, 1.0, 0.0, 0.85], [0.0, 0.0, -1.0, 0.95]]])
+    depth, rgb = render_frames(scene, cam, poses)
+    assert ((depth.numpy() > 1.9) & (depth.numpy() < 2.0)).all()
+    G, O = make_pair(vbh, orc, vol, cam)
+    integrate_both(G, O, depth, rgb, poses, range(2))
+    keys = O.blocks()
+    bz = keys[:, 2].astype(np.int64)
+    say(f"  block z from {bz.min()} to {bz.max()} (camera blocks {int(np.floor(-0.95 / 0.004))}, {int(np.floor(0.95 / 0.004))})")
+    assert bz.max() - int(np.floor(-0.95 / 0.004)) >= 480 and int(np.floor(0.95 / 0.004)) - bz.min() >= 480
+    k2, F2, W2, rgb2, gmc, grgb = compare_state(G, O)
     mc_on_identical_input(orc, vol, cam, k2, F2, W2, rgb2, gmc, grgb)
 
 
