@@ -105,7 +105,7 @@ int orc_scene_error(void *s);
  * update inserts its update set into every client's set (a block already pending keeps
  * one entry, carrying the newest update's frame id).  A request of size limit removes
  * min(limit, |set|) blocks and sends them with their current MC voxels.  The paper takes
- * a random subset; this build's reading sends the oldest updates first, leaving free only
+ * a random subset; the reading taken here sends the oldest updates first, leaving free only
  * the order among blocks of the same update.  A (re)connecting client's set holds every
  * block of the model.
  * The streams follow a scene's update log: orc_streams_sync absorbs the entries appended

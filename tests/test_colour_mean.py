@@ -9,7 +9,6 @@ definition for every stored weight W in 0..255, stored colour c and observed col
 c_obs in 0..255, and reciprocals 0, 1 and 2 ulps either side of the correctly rounded
 1/n: 16.7M triples times 5 reciprocals.  Dropping the half (a plausible mistake, which
 takes away the 1/(2n) margin to the nearest integer) fails."""
-import os
 import subprocess
 
 import pytest

@@ -1,6 +1,6 @@
 """Pins of two readings of the paper that no uniform input can tell apart.
 
-- MC voxel colour (the paper sends one colour per MC voxel, Sec. 4.2; this build's reading:
+- MC voxel colour (the paper sends one colour per MC voxel, Sec. 4.2; the reading taken here:
   the colour of the cell's corner-0 voxel).  Every voxel gets a colour of its own, so the
   expected colour of each surface cell is the hand-derived colour of its corner 0.
 - The running mean at saturation (weight 1 per observation, W capped at 255, and then
